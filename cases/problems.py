@@ -1,0 +1,87 @@
+"""Named synthetic workloads: mesh + initial state + boundary data + constants.
+
+A problem is a plain dict of inputs:
+  xyz     (3, nth, nr, nx) float64 coordinates
+  Q       (5, nth, nr, nx) float64 conserved state
+  inflow  (5, nth, nr) float64 inflow target primitives, or None
+  params  dict of scalar constants and boundary kinds (see `base_params`)
+The solver (GPU library) and the CPU oracle each consume these inputs their
+own way; nothing here computes any part of the residual.
+"""
+import math
+
+import torch
+
+from . import flow, mesh
+
+RK_ALPHA = (1.0 / 4.0, 1.0 / 6.0, 3.0 / 8.0, 1.0 / 2.0, 1.0)   # Jameson 5-stage
+
+
+def base_params(**over):
+    """Physical and numerical constants.
+
+    gamma = 1.4, Pr = 0.72, Pr_sgs = 0.9 (static SGS models), k2 = 0.25,
+    k4 = 0.016 (Turkel-Vatsa constants), Cs = 0.148 (Lilly),
+    Sutherland S1 = 110.4 K over a 288.15 K reference temperature.
+    visc_coef = M/Re multiplies the viscous fluxes.
+    bc order: xi-, xi+, eta-, eta+, zeta-, zeta+.
+    """
+    p = dict(gamma=1.4, Pr=0.72, Pr_sgs=0.9, visc_coef=0.0,
+             suth_S=110.4 / 288.15, Cs=0.148, k2=0.25, k4=0.016, cfl=0.5,
+             rk_alpha=RK_ALPHA, ref_prim=(1.0, 0.0, 0.0, 0.0, 1.0 / 1.4),
+             p_exit=1.0 / 1.4, sgs_model=1,
+             bc=("periodic",) * 6,
+             period=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    p.update(over)
+    return p
+
+
+def box_params(L=2.0 * math.pi, **over):
+    p = base_params(visc_coef=0.5 / 1.0e4,
+                    period=((L, 0.0, 0.0), (0.0, L, 0.0), (0.0, 0.0, L)))
+    p.update(over)
+    return p
+
+
+def jet_params(**over):
+    g = 1.4
+    p = base_params(visc_coef=flow.JET_UJ / 1.5e6,
+                    ref_prim=(1.0, flow.JET_UCO, 0.0, 0.0, 1.0 / g),
+                    p_exit=1.0 / g,
+                    bc=("inflow", "outflow", "axis", "farfield", "periodic", "periodic"))
+    p.update(over)
+    return p
+
+
+def box_problem(n=32, seed=1, Cs=0.148, noise=1e-4, shape=None):
+    """Periodic box, L = 2 pi, isentropic Mach-0.5 vortex plus noise."""
+    L = 2.0 * math.pi
+    xyz = mesh.box_coords(n, L, shape=shape)
+    Q = flow.vortex_box_state(xyz, seed=seed, noise=noise)
+    return dict(name=f"box{n}", xyz=xyz, Q=Q, inflow=None,
+                params=box_params(L, Cs=Cs))
+
+
+def jet_grid(nx, nr, nth):
+    return mesh.jet_axial(nx), mesh.jet_radial(nr), mesh.azimuth(nth)
+
+
+def jet_problem(nx, nr, nth, seed=2, coef=None, noise=1e-3 * flow.JET_UJ,
+                with_xyz=True, device="cpu"):
+    """Cylindrical jet mesh with the Mach-1.4 parallel-jet state."""
+    X, R, TH = jet_grid(nx, nr, nth)
+    xyz = mesh.cylindrical_coords(X, R, TH, device=device) if with_xyz else None
+    Q = flow.jet_state(X, R, TH, seed=seed, coef=coef, noise=noise, device=device)
+    inflow = flow.jet_inflow(R, TH, seed=seed, coef=coef, noise=noise, device=device)
+    return dict(name=f"jet{nx}x{nr}x{nth}", xyz=xyz, Q=Q, inflow=inflow,
+                params=jet_params(), grid=(X, R, TH))
+
+
+# the configurations the measurements and parity tests are run on
+CONFIGS = {
+    "box32": dict(kind="box", n=32, steps=10, seed=1),
+    "jet5.9M": dict(kind="jet", shape=(288, 160, 128), steps=100, seed=2),
+    "prec102M": dict(kind="jet", shape=(800, 400, 320), steps=50, seed=3),
+    "adj2M": dict(kind="jet", shape=(160, 100, 128), steps=20, seed=4),
+    "big1B": dict(kind="jet", shape=(1250, 640, 1250), steps=20, seed=2),
+}

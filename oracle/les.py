@@ -1,0 +1,564 @@
+"""Plain, slow FP64 NumPy oracle of the explicit LES residual and RK5 step.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+the benchmark's CPU-baseline leg import this module; the GPU library never
+calls it and shares no code with it.
+
+What it computes, in the order of the paper (Junqueira-Junior et al., "A LES
+solver for supersonic jet flows", arXiv 2301.00817):
+  * metrics and Jacobian of the curvilinear transformation
+    (section "Transformation of Coordinates", metric-term and Jacobian
+    equations);
+  * ghost values from the boundary conditions (section "Boundary Conditions":
+    far field by Riemann invariants, entrance, exit, centerline, periodic);
+  * the residual RHS/V of the semi-discrete system (section "Spatial
+    Discretization", eq. spatial_discret and the RHS equation), built from
+    centred inviscid point fluxes (eq. hat-flux-G), viscous and SGS point
+    fluxes (eqs. hat-flux-Ev/Fv/Gv, q_mod, kappa_sgs, tau_mod, sutherland,
+    Smagorinsky model), and the Turkel-Vatsa artificial dissipation
+    (eqs. inv_flux_vec, dissip_term, eps_2_dissip, eps_4_dissip,
+    p_grad_sensor, W_dissip, spectral radii);
+  * the five-stage Runge-Kutta step (section "Time Marching Method",
+    eq. localdt and the alpha coefficients).
+
+Readings taken where the paper is silent, garbled or inconsistent (each is
+also listed in the design notes):
+  R1  the state is stored unhatted, Q = (rho, rho u, rho v, rho w, E); the
+      dissipation vector is W = (rho, rho u, rho v, rho w, E + p) and the
+      face factor J^-1 is the face average V_f = (V_L + V_R)/2.
+  R2  the operator between the eps2 and eps4 terms of the dissipation is a
+      minus sign (the standard, dissipative choice).
+  R3  the pressure sensor denominator is p+ + 2p + p- (the printed
+      p+ - 2p + p- would make the sensor identically 1).
+  R4  lambda_d = |U_d| + a |grad xi_d| for d = xi, eta, zeta (the printed
+      three rows are all labelled lambda_xi with one mixed norm).
+  R5  the eta metric row is the cofactor grad eta = J (r_zeta x r_xi).
+  R6  heat flux q = -(kappa + kappa_sgs) grad T (down-gradient).
+  R7  Smagorinsky mu_sgs = rho (Cs Delta)^2 |S|; in units of the jet
+      viscosity it is divided by visc_coef = M/Re.
+  R9  filter width Delta = |V|^(1/3).
+  R10 Sutherland mu = T^1.5 (1 + S)/(T + S), S = 110.4 K / 288.15 K.
+  R11 viscous face flux = average of the two point viscous fluxes, with point
+      gradients by central differences and the chain rule (R12).
+  R13 mu and mu_sgs are recomputed from the state at every evaluation.
+  R14 ghosts are refilled before every residual evaluation.
+  R15 dissipation is zero on physical-boundary faces (entrance, exit, far
+      field); periodic and cross-axis faces are internal.
+  R18 one global time step dt = CFL / max(lambda_xi + lambda_eta + lambda_zeta)
+      over the interior of Q^n, or a fixed dt.
+  R19 periodic azimuth with n_theta distinct points (no duplicated point).
+  R20 the mesh has no node on the axis; the ghosts across the axis are the
+      points (i, m, k + n_theta/2), coordinates and state copied.
+  R21 entrance: a supersonic target (normal Mach >= 1) is imposed; otherwise
+      Riemann invariants with the outward normal -xi and the target as the
+      outside state.
+  R22 exit: subsonic -> rho, u, v, w from the last interior plane and
+      p = p_exit; supersonic -> copy.
+  R23 R+ = q_e + 2 a_e/(gamma-1), and the velocity is corrected along the
+      unit normal.
+  R24 branch ties: q/a >= 1 exit copy, q/a <= -1 outside state, q >= 0
+      subsonic exit.
+
+The code is dtype-generic: complex128 arrays give complex-step derivatives
+(abs, max and branch tests act on real parts).
+"""
+import numpy as np
+
+NG = 2      # ghost layers of the state and metric arrays
+NGC = 3     # ghost layers of the coordinate array
+
+PHYSICAL_FACE_KINDS = ("inflow", "outflow", "farfield")
+
+
+# ---------------------------------------------------------------------------
+# complex-safe elementary operations
+# ---------------------------------------------------------------------------
+def rabs(x):
+    """|x| acting on the real part (identity derivative sign for x >= 0)."""
+    return np.where(np.real(x) < 0, -x, x)
+
+
+def rmax(a, b):
+    return np.where(np.real(a) >= np.real(b), a, b)
+
+
+# ---------------------------------------------------------------------------
+# layout helpers: arrays are (..., zeta, eta, xi) with xi fastest
+# ---------------------------------------------------------------------------
+def _axis(A, d):
+    """Array axis of spatial direction d (0 = xi, 1 = eta, 2 = zeta)."""
+    return A.ndim - 1 - d
+
+
+def _fill_region(A, d, g):
+    """View of A with direction d last, restricted in the other directions to
+    what is defined when direction d is filled (fill order xi, eta, zeta):
+    xi is filled on the interior of eta and zeta, eta on the interior of
+    zeta (all xi), zeta everywhere."""
+    sl = [slice(None)] * A.ndim
+    if d == 0:
+        sl[_axis(A, 1)] = slice(g, -g)
+        sl[_axis(A, 2)] = slice(g, -g)
+    elif d == 1:
+        sl[_axis(A, 2)] = slice(g, -g)
+    return np.moveaxis(A[tuple(sl)], _axis(A, d), -1)
+
+
+# ---------------------------------------------------------------------------
+# geometry: coordinate ghosts and metrics
+# ---------------------------------------------------------------------------
+def pad_coords(xyz, prm):
+    """Coordinates (3, nth, nr, nx) -> padded (3, nth+6, nr+6, nx+6).
+
+    Ghost rules per boundary kind: periodic -> wrapped interior point plus the
+    period translation; axis -> the point across the axis (i, m, k+nth/2);
+    entrance/exit/far field -> linear extrapolation in index space,
+    r_{-m} = r_0 + m (r_0 - r_1)."""
+    g = NGC
+    _, nth, nr, nx = xyz.shape
+    n = (nx, nr, nth)
+    P = np.full((3, nth + 2 * g, nr + 2 * g, nx + 2 * g), np.nan, dtype=xyz.dtype)
+    P[:, g:g + nth, g:g + nr, g:g + nx] = xyz
+    period = np.asarray(prm["period"], dtype=float)
+    for d in range(3):
+        lo_kind, hi_kind = prm["bc"][2 * d], prm["bc"][2 * d + 1]
+        L = _fill_region(P, d, g)                   # (3, a, b, n_d + 2g)
+        nd = n[d]
+        shift = period[d].reshape(3, 1, 1)
+        for m in range(1, g + 1):
+            lo, hi = g - m, g + nd - 1 + m
+            if lo_kind == "periodic":
+                L[..., lo] = L[..., g + nd - m] - shift
+            elif lo_kind == "axis":
+                # eta direction: the other (zeta) axis of L is axis 1
+                L[..., lo] = np.roll(L[..., g + m - 1], -(n[2] // 2), axis=1)
+            else:
+                L[..., lo] = L[..., g] + m * (L[..., g] - L[..., g + 1])
+            if hi_kind == "periodic":
+                L[..., hi] = L[..., g + m - 1] + shift
+            else:
+                L[..., hi] = L[..., g + nd - 1] + m * (L[..., g + nd - 1] - L[..., g + nd - 2])
+    return P
+
+
+def metrics(P):
+    """Metric terms on the state's padded box (two ghost layers).
+
+    Derivatives of the coordinates are second-order central differences in
+    index space (unit spacing).  Returns
+      S : (3, 3, nth+4, nr+4, nx+4), S[d] = J^-1 grad(xi_d) (area vectors)
+      V : (nth+4, nr+4, nx+4), V = J^-1 (the Jacobian determinant).
+    The rows are the paper's metric-term formulas multiplied by J^-1; the eta
+    row is the cofactor r_zeta x r_xi (reading R5)."""
+    def central(ax):
+        hi = [slice(None), slice(1, -1), slice(1, -1), slice(1, -1)]
+        lo = list(hi)
+        hi[ax] = slice(2, None)
+        lo[ax] = slice(None, -2)
+        return (P[tuple(hi)] - P[tuple(lo)]) / 2.0
+
+    x_xi, y_xi, z_xi = central(3)
+    x_eta, y_eta, z_eta = central(2)
+    x_zeta, y_zeta, z_zeta = central(1)
+
+    S = np.empty((3, 3) + x_xi.shape, dtype=P.dtype)
+    # J^-1 (xi_x, xi_y, xi_z)
+    S[0, 0] = y_eta * z_zeta - y_zeta * z_eta
+    S[0, 1] = z_eta * x_zeta - z_zeta * x_eta
+    S[0, 2] = x_eta * y_zeta - x_zeta * y_eta
+    # J^-1 (eta_x, eta_y, eta_z)
+    S[1, 0] = y_zeta * z_xi - y_xi * z_zeta
+    S[1, 1] = z_zeta * x_xi - z_xi * x_zeta
+    S[1, 2] = x_zeta * y_xi - x_xi * y_zeta
+    # J^-1 (zeta_x, zeta_y, zeta_z)
+    S[2, 0] = y_xi * z_eta - y_eta * z_xi
+    S[2, 1] = z_xi * x_eta - z_eta * x_xi
+    S[2, 2] = x_xi * y_eta - x_eta * y_xi
+    # J^-1 = x_xi y_eta z_zeta + x_eta y_zeta z_xi + x_zeta y_xi z_eta
+    #        - x_xi y_zeta z_eta - x_eta y_xi z_zeta - x_zeta y_eta z_xi
+    V = (x_xi * y_eta * z_zeta + x_eta * y_zeta * z_xi + x_zeta * y_xi * z_eta
+         - x_xi * y_zeta * z_eta - x_eta * y_xi * z_zeta - x_zeta * y_eta * z_xi)
+    return dict(S=S, V=V)
+
+
+def geometry(xyz, prm):
+    """pad_coords + metrics."""
+    return metrics(pad_coords(np.asarray(xyz), prm))
+
+
+# ---------------------------------------------------------------------------
+# state conversions
+# ---------------------------------------------------------------------------
+def primitives(Q, gamma):
+    """(rho, u, v, w, p) from Q = (rho, rho u, rho v, rho w, E), with
+    E = p/(gamma-1) + rho |u|^2/2 (System-I energy)."""
+    rho = Q[0]
+    u = Q[1] / rho
+    v = Q[2] / rho
+    w = Q[3] / rho
+    p = (gamma - 1.0) * (Q[4] - 0.5 * rho * (u * u + v * v + w * w))
+    return rho, u, v, w, p
+
+
+def conserved(rho, u, v, w, p, gamma):
+    return np.stack([rho, rho * u, rho * v, rho * w,
+                     p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
+
+
+def pad_state(Q):
+    """Interior (5, nth, nr, nx) -> padded (5, nth+4, nr+4, nx+4); ghosts NaN
+    until fill_ghosts runs."""
+    g = NG
+    _, nth, nr, nx = Q.shape
+    Qp = np.full((5, nth + 2 * g, nr + 2 * g, nx + 2 * g), np.nan, dtype=Q.dtype)
+    Qp[:, g:-g, g:-g, g:-g] = Q
+    return Qp
+
+
+def interior(A):
+    g = NG
+    return A[..., g:-g, g:-g, g:-g]
+
+
+# ---------------------------------------------------------------------------
+# boundary conditions (section "Boundary Conditions")
+# ---------------------------------------------------------------------------
+def riemann_state(e, r, n, gamma):
+    """Boundary state from Riemann invariants (far-field subsection).
+
+    e, r: primitives (rho, u, v, w, p) inside / outside; n: outward unit
+    normal (3, ...).  R+ = q_e + 2 a_e/(gamma-1), R- = q_r - 2 a_r/(gamma-1),
+    q_f = (R+ + R-)/2, a_f = (gamma-1)(R+ - R-)/4.  Branches on M = q_e/a_e:
+    M >= 1 interior state; M <= -1 outside state; q_e >= 0 subsonic exit
+    (velocity corrected along n, entropy of e); else subsonic entrance
+    (velocity corrected along n, entropy of r).  Returns primitives and the
+    branch masks (sup_out, sup_in, sub_out)."""
+    re, ue, ve, we, pe = e
+    rr, ur, vr, wr, pr = r
+    ae = np.sqrt(gamma * pe / re)
+    ar = np.sqrt(gamma * pr / rr)
+    qe = ue * n[0] + ve * n[1] + we * n[2]
+    qr = ur * n[0] + vr * n[1] + wr * n[2]
+    Rp = qe + 2.0 * ae / (gamma - 1.0)
+    Rm = qr - 2.0 * ar / (gamma - 1.0)
+    qf = 0.5 * (Rp + Rm)
+    af = 0.25 * (gamma - 1.0) * (Rp - Rm)
+    # subsonic exit: from the interior
+    rho_o = (re ** gamma * af * af / (gamma * pe)) ** (1.0 / (gamma - 1.0))
+    out = (rho_o,
+           ue + (qf - qe) * n[0], ve + (qf - qe) * n[1], we + (qf - qe) * n[2],
+           rho_o * af * af / gamma)
+    # subsonic entrance: from the outside state
+    rho_i = (rr ** gamma * af * af / (gamma * pr)) ** (1.0 / (gamma - 1.0))
+    inn = (rho_i,
+           ur + (qf - qr) * n[0], vr + (qf - qr) * n[1], wr + (qf - qr) * n[2],
+           rho_i * af * af / gamma)
+    M = np.real(qe / ae)
+    sup_out = M >= 1.0
+    sup_in = M <= -1.0
+    sub_out = np.real(qe) >= 0.0
+    f = []
+    for c in range(5):
+        rc = np.broadcast_to(r[c], np.shape(e[c]))
+        f.append(np.where(sup_out, e[c], np.where(sup_in, rc,
+                                                  np.where(sub_out, out[c], inn[c]))))
+    return f, (sup_out, sup_in & ~sup_out, sub_out & ~sup_out & ~sup_in)
+
+
+def _unit(Svec):
+    mag = np.sqrt(Svec[0] * Svec[0] + Svec[1] * Svec[1] + Svec[2] * Svec[2])
+    return Svec / mag
+
+
+def fill_ghosts(Qp, geo, prm, inflow=None):
+    """Fill the two ghost layers of the padded state in place.
+
+    Order xi, eta, zeta (so that edge ghosts read already-filled values):
+      xi-  periodic | entrance (data `inflow` = target primitives (5, nth, nr))
+      xi+  periodic | exit (back pressure p_exit)
+      eta- periodic | centerline: copy of (i, m, k + nth/2), m = 0, 1
+      eta+ periodic | far field: Riemann invariants with the reference state
+      zeta periodic (all i, j).
+    Both ghost layers of a non-periodic face receive the same face state."""
+    g = NG
+    gamma = prm["gamma"]
+    bc = prm["bc"]
+    S, V = geo["S"], geo["V"]
+    _, nthp, nrp, nxp = Qp.shape
+    nth, nr, nx = nthp - 2 * g, nrp - 2 * g, nxp - 2 * g
+    n = (nx, nr, nth)
+
+    for d in range(3):
+        lo_kind, hi_kind = bc[2 * d], bc[2 * d + 1]
+        L = _fill_region(Qp, d, g)                  # (5, a, b, n_d + 2g)
+        Sd = _fill_region(S[d], d, g)               # (3, a, b, n_d + 2g)
+        nd = n[d]
+        # periodic wraps
+        if lo_kind == "periodic":
+            for m in range(1, g + 1):
+                L[..., g - m] = L[..., g + nd - m]
+        if hi_kind == "periodic":
+            for m in range(1, g + 1):
+                L[..., g + nd - 1 + m] = L[..., g + m - 1]
+
+        if lo_kind == "axis":
+            for m in range(1, g + 1):
+                L[..., g - m] = np.roll(L[..., g + m - 1], -(n[2] // 2), axis=1)
+
+        if lo_kind == "inflow":
+            Qe = L[..., g]
+            e = primitives(Qe, gamma)
+            nrm = -_unit(Sd[..., g])                # outward normal at the entrance
+            tgt = [np.asarray(inflow[c]) for c in range(5)]   # (nth, nr), like L[..., g]
+            at = np.sqrt(gamma * tgt[4] / tgt[0])
+            mn = -(tgt[1] * nrm[0] + tgt[2] * nrm[1] + tgt[3] * nrm[2]) / at
+            f, (sup_out, _, _) = riemann_state(e, tgt, nrm, gamma)
+            sup = np.real(mn) >= 1.0
+            Qf = np.where(sup, conserved(*tgt, gamma),
+                          np.where(sup_out, Qe, conserved(*f, gamma)))
+            for m in range(1, g + 1):
+                L[..., g - m] = Qf
+
+        if hi_kind == "outflow":
+            Qe = L[..., g + nd - 1]
+            e = primitives(Qe, gamma)
+            nrm = _unit(Sd[..., g + nd - 1])
+            ae = np.sqrt(gamma * e[4] / e[0])
+            qe = e[1] * nrm[0] + e[2] * nrm[1] + e[3] * nrm[2]
+            sup = np.real(qe / ae) >= 1.0
+            Qsub = conserved(e[0], e[1], e[2], e[3],
+                             np.full_like(e[4], prm["p_exit"]), gamma)
+            Qf = np.where(sup, Qe, Qsub)
+            for m in range(1, g + 1):
+                L[..., g + nd - 1 + m] = Qf
+
+        if hi_kind == "farfield":
+            Qe = L[..., g + nd - 1]
+            e = primitives(Qe, gamma)
+            nrm = _unit(Sd[..., g + nd - 1])
+            ref = [np.asarray(c, dtype=float) for c in prm["ref_prim"]]
+            f, (sup_out, _, _) = riemann_state(e, ref, nrm, gamma)
+            Qf = np.where(sup_out, Qe, conserved(*f, gamma))
+            for m in range(1, g + 1):
+                L[..., g + nd - 1 + m] = Qf
+    return Qp
+
+
+# ---------------------------------------------------------------------------
+# residual (section "Spatial Discretization")
+# ---------------------------------------------------------------------------
+def _lines(A, d, ng):
+    """Direction-d lines of A at the interior of the two other directions
+    (ng = ghost count of A along those directions); direction d last."""
+    sl = [slice(None)] * A.ndim
+    for dd in range(3):
+        if dd != d:
+            sl[_axis(A, dd)] = slice(ng, -ng)
+    return np.moveaxis(A[tuple(sl)], _axis(A, d), -1)
+
+
+def point_terms(Qp, geo, prm):
+    """Point quantities on the region where every index is in [-1, n].
+
+    Returns dict with (arrays over that region, shape (.., nth+2, nr+2, nx+2)):
+      G[d]    = Fe^d - Fv^d, the inviscid minus viscous point flux (5 comps)
+      lam[d]  = spectral radius lambda_d, lam_bar[d] its anisotropic scaling
+      nu[d]   = pressure sensor along d
+      mu_t    = SGS eddy viscosity (in jet-viscosity units)
+    and W over the whole padded box."""
+    gamma = prm["gamma"]
+    Cv = prm["visc_coef"]
+    S_all, V_all = geo["S"], geo["V"]
+    rho, u, v, w, p = primitives(Qp, gamma)
+    E = Qp[4]
+    T = gamma * p / rho                 # p = rho T / gamma (equation of state)
+    a = np.sqrt(gamma * p / rho)
+
+    c = (slice(1, -1),) * 3             # region one
+    S = S_all[(slice(None), slice(None)) + c]
+    V = V_all[c]
+    r1 = lambda A: A[c]  # noqa: E731
+
+    def delta(phi, d):
+        """(phi_{+1} - phi_{-1})/2 along direction d, on region one."""
+        ax = 2 - d
+        hi = [slice(1, -1)] * 3
+        lo = [slice(1, -1)] * 3
+        hi[ax] = slice(2, None)
+        lo[ax] = slice(None, -2)
+        return (phi[tuple(hi)] - phi[tuple(lo)]) / 2.0
+
+    def grad(phi):
+        """Cartesian gradient by the chain rule: d phi/d x_m =
+        sum_d (J^-1 grad xi_d)_m delta_d phi / J^-1."""
+        dd = [delta(phi, d) for d in range(3)]
+        return [(S[0, m] * dd[0] + S[1, m] * dd[1] + S[2, m] * dd[2]) / V
+                for m in range(3)]
+
+    out = {}
+    # inviscid point fluxes (eq. hat-flux-G, contravariant velocity times J^-1)
+    ru, rv, rw = r1(Qp[1]), r1(Qp[2]), r1(Qp[3])
+    rho1, u1, v1, w1, p1, E1 = r1(rho), r1(u), r1(v), r1(w), r1(p), r1(E)
+    Uc = [S[d, 0] * u1 + S[d, 1] * v1 + S[d, 2] * w1 for d in range(3)]
+    Fe = [np.stack([rho1 * Uc[d],
+                    ru * Uc[d] + p1 * S[d, 0],
+                    rv * Uc[d] + p1 * S[d, 1],
+                    rw * Uc[d] + p1 * S[d, 2],
+                    (E1 + p1) * Uc[d]]) for d in range(3)]
+
+    # viscous and SGS point fluxes (eqs. tau_mod, q_mod, hat-flux-Ev/Fv/Gv)
+    if Cv != 0.0:
+        Ssuth = prm["suth_S"]
+        T1 = r1(T)
+        mu = T1 ** 1.5 * (1.0 + Ssuth) / (T1 + Ssuth)      # Sutherland (R10)
+        gu = [grad(u), grad(v), grad(w)]                    # gu[i][m] = d u_i / d x_m
+        gT = grad(T)
+        div = gu[0][0] + gu[1][1] + gu[2][2]
+        if prm["sgs_model"] == 1 and prm["Cs"] != 0.0:
+            Sij2 = 0.0
+            for i in range(3):
+                for j in range(3):
+                    sij = 0.5 * (gu[i][j] + gu[j][i])
+                    Sij2 = Sij2 + sij * sij
+            Smag = np.sqrt(2.0 * Sij2)
+            delta_f = rabs(V) ** (1.0 / 3.0)                # filter width (R9)
+            mu_t = rho1 * (prm["Cs"] * delta_f) ** 2 * Smag / Cv   # (R7)
+        else:
+            mu_t = np.zeros_like(mu)
+        out["mu_t"] = mu_t
+        tau = [[(mu + mu_t) * (gu[i][j] + gu[j][i] - (2.0 / 3.0 if i == j else 0.0) * div)
+                for j in range(3)] for i in range(3)]
+        kap = (mu / prm["Pr"] + mu_t / prm["Pr_sgs"]) / (gamma - 1.0)
+        q = [-kap * gT[j] for j in range(3)]                # (R6)
+        vel = (u1, v1, w1)
+        beta = [tau[0][j] * vel[0] + tau[1][j] * vel[1] + tau[2][j] * vel[2] - q[j]
+                for j in range(3)]
+        Fv = []
+        for d in range(3):
+            Fv.append(Cv * np.stack([
+                np.zeros_like(u1),
+                S[d, 0] * tau[0][0] + S[d, 1] * tau[0][1] + S[d, 2] * tau[0][2],
+                S[d, 0] * tau[1][0] + S[d, 1] * tau[1][1] + S[d, 2] * tau[1][2],
+                S[d, 0] * tau[2][0] + S[d, 1] * tau[2][1] + S[d, 2] * tau[2][2],
+                S[d, 0] * beta[0] + S[d, 1] * beta[1] + S[d, 2] * beta[2]]))
+        out["G"] = [Fe[d] - Fv[d] for d in range(3)]
+    else:
+        out["G"] = Fe
+
+    # dissipation ingredients (spectral radii R4, sensor R3, W R1)
+    a1 = r1(a)
+    Smag_d = [np.sqrt(S[d, 0] ** 2 + S[d, 1] ** 2 + S[d, 2] ** 2) for d in range(3)]
+    lam = [(rabs(Uc[d]) + a1 * Smag_d[d]) / rabs(V) for d in range(3)]
+    lam_bar = []
+    for d in range(3):
+        o1, o2 = lam[(d + 1) % 3], lam[(d + 2) % 3]
+        lam_bar.append(lam[d] * (1.0 + np.sqrt(o1 / lam[d]) + np.sqrt(o2 / lam[d])))
+    nu = []
+    for d in range(3):
+        ax = 2 - d
+        hi = [slice(1, -1)] * 3
+        lo = [slice(1, -1)] * 3
+        hi[ax] = slice(2, None)
+        lo[ax] = slice(None, -2)
+        pp, pm = p[tuple(hi)], p[tuple(lo)]
+        nu.append(rabs(pp - 2.0 * p1 + pm) / (pp + 2.0 * p1 + pm))
+    out.update(lam=lam, lam_bar=lam_bar, nu=nu, V=V,
+               W=np.stack([Qp[0], Qp[1], Qp[2], Qp[3], Qp[4] + p]))
+    return out
+
+
+def face_fluxes(pt, d, prm):
+    """Numerical fluxes at the faces -1/2 .. n_d - 1/2 along direction d
+    (eq. inv_flux_vec with the dissipation of eq. dissip_term), on the
+    interior of the two other directions.  Shape (5, ..., n_d + 1)."""
+    G = _lines(pt["G"][d], d, 1)           # (5, a, b, n_d + 2): points -1 .. n_d
+    lb = _lines(pt["lam_bar"][d], d, 1)
+    nu = _lines(pt["nu"][d], d, 1)
+    V = _lines(pt["V"], d, 1)
+    W = _lines(pt["W"], d, 2)              # (5, a, b, n_d + 4): points -2 .. n_d + 1
+    GL, GR = G[..., :-1], G[..., 1:]       # L = -1 .. n_d - 1
+    eps2 = prm["k2"] * rmax(nu[..., :-1], nu[..., 1:])
+    eps4 = rmax(0.0 * eps2, prm["k4"] - eps2)
+    lam_f = 0.5 * (lb[..., :-1] + lb[..., 1:])
+    V_f = 0.5 * (V[..., :-1] + V[..., 1:])
+    Wm, WL, WR, Wp = W[..., :-3], W[..., 1:-2], W[..., 2:-1], W[..., 3:]
+    dis = lam_f * (eps2 * (WR - WL) - eps4 * (Wp - 3.0 * WR + 3.0 * WL - Wm))
+    lo_kind, hi_kind = prm["bc"][2 * d], prm["bc"][2 * d + 1]
+    if lo_kind in PHYSICAL_FACE_KINDS:     # R15
+        dis[..., 0] = 0.0
+    if hi_kind in PHYSICAL_FACE_KINDS:
+        dis[..., -1] = 0.0
+    return 0.5 * (GL + GR) - V_f * dis
+
+
+def residual(Qp, geo, prm):
+    """R = RHS / V on the interior, for a padded state whose ghosts are
+    filled; dQ/dt = -R (eq. spatial_discret with unit index spacing)."""
+    pt = point_terms(Qp, geo, prm)
+    g = NG
+    _, nthp, nrp, nxp = Qp.shape
+    rhs = 0.0
+    for d in range(3):
+        F = face_fluxes(pt, d, prm)
+        diff = F[..., 1:] - F[..., :-1]
+        rhs = rhs + np.moveaxis(diff, -1, diff.ndim - 1 - d)
+    return rhs / interior(geo["V"])
+
+
+def lambda_sum(Qp, geo, prm):
+    """lambda_xi + lambda_eta + lambda_zeta on the interior."""
+    gamma = prm["gamma"]
+    Q = interior(Qp)
+    S = interior(geo["S"])
+    V = interior(geo["V"])
+    rho, u, v, w, p = primitives(Q, gamma)
+    a = np.sqrt(gamma * p / rho)
+    tot = 0.0
+    for d in range(3):
+        Uc = S[d, 0] * u + S[d, 1] * v + S[d, 2] * w
+        tot = tot + (rabs(Uc) + a * np.sqrt(S[d, 0] ** 2 + S[d, 1] ** 2 + S[d, 2] ** 2)) / rabs(V)
+    return tot
+
+
+def time_step(Q, geo, prm):
+    """Global dt = CFL / max_interior(lambda sum) (reading R18)."""
+    Qp = pad_state(Q)
+    return prm["cfl"] / np.max(np.real(lambda_sum(Qp, geo, prm)))
+
+
+def evaluate(Q, geo, prm, inflow=None):
+    """Residual of an interior state: pad, fill ghosts, residual."""
+    Qp = pad_state(np.asarray(Q))
+    fill_ghosts(Qp, geo, prm, inflow)
+    return residual(Qp, geo, prm)
+
+
+# ---------------------------------------------------------------------------
+# time marching (section "Time Marching Method")
+# ---------------------------------------------------------------------------
+def jameson_rk(Q0, resid, dt, alpha):
+    """Q^(l) = Q^(0) - alpha_l dt R(Q^(l-1)), l = 1..len(alpha); returns the
+    last stage.  `resid` maps a state to R."""
+    Q = Q0
+    for a in alpha:
+        Q = Q0 - a * dt * resid(Q)
+    return Q
+
+
+def rk5_step(Q, geo, prm, inflow=None, dt=None):
+    """One RK5 time step of the interior state Q; dt from CFL when None.
+    Returns (Q^{n+1}, dt)."""
+    if dt is None:
+        dt = time_step(Q, geo, prm)
+    Qn = jameson_rk(np.asarray(Q), lambda q: evaluate(q, geo, prm, inflow), dt,
+                    prm["rk_alpha"])
+    return Qn, dt
+
+
+def run(Q, geo, prm, inflow=None, steps=1, dt=None):
+    """`steps` RK5 steps; returns (Q, list of dt)."""
+    dts = []
+    for _ in range(steps):
+        Q, h = rk5_step(Q, geo, prm, inflow, dt)
+        dts.append(h)
+    return Q, dts

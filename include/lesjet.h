@@ -1,0 +1,183 @@
+/*
+ * lesjet — explicit LES residual and five-stage Runge-Kutta step of the
+ * filtered compressible Navier-Stokes equations (System-I energy form) on a
+ * structured curvilinear mesh, for one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Junqueira-Junior, Azevedo, Yamouni, Wolf, arXiv 2301.00817,
+ * sections "Large Eddy Simulation Filtering", "Subgrid Scale Modeling"
+ * (static Smagorinsky), "Transformation of Coordinates", "Numerical
+ * Formulation" (centred fluxes, Turkel-Vatsa artificial dissipation, Jameson
+ * 5-stage RK) and "Boundary Conditions".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Index directions: xi (i, axial, fastest in memory), eta (j, radial),
+ * zeta (k, azimuthal).  Interior sizes nx, nr, nth.
+ *
+ * Padded field layout: a field of `nvar` variables is stored as
+ *     F[v][k + 2][j + 2][i + 2],  i in [-2, nx+1], j in [-2, nr+1], k in [-2, nth+1]
+ * with row pitch `pitch` elements (>= nx + 4, from les_layout), plane stride
+ * (nr + 4) * pitch and variable stride (nth + 4) * (nr + 4) * pitch.
+ * Two ghost layers on every face hold boundary / periodic values; the
+ * library writes them (they are scratch from the caller's point of view).
+ *
+ * State Q: unhatted nondimensional conserved variables
+ *     (rho, rho u, rho v, rho w, E),  E = p/(gamma-1) + rho |u|^2 / 2,
+ * scaled by the jet density, jet sound speed and diameter
+ * ("Dimensionless Formulation").  Residual R: dQ/dt = -R, R = RHS / J^-1
+ * (eq. spatial_discret with unit index spacing).
+ *
+ * Pointers: arguments documented "device" are HIP device pointers owned by
+ * the caller (e.g. torch tensor storage); "host" pointers are read during
+ * the call only.  The library owns its context, metrics, stage buffers and
+ * scratch, released by les_free.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = default stream).  Work is
+ * enqueued asynchronously unless stated otherwise.  A context must not be
+ * used from two host threads at once, nor on two streams concurrently.
+ *
+ * Errors: every function returns LES_OK (0) or a negative code; nothing
+ * aborts and no C++ exception crosses the ABI.  Arguments are validated
+ * before any device work.  les_last_error gives a message.
+ */
+#ifndef LESJET_H
+#define LESJET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct les_ctx les_ctx;
+
+enum les_status {
+  LES_OK = 0,
+  LES_EINVAL = -1,        /* bad argument (sizes, pointers, boundary kinds) */
+  LES_ENOMEM = -2,        /* device allocation failed */
+  LES_EHIP = -3,          /* a HIP runtime call failed (message has details) */
+  LES_ENONFINITE = -4,    /* time-step reduction met a NaN/Inf (diverged state) */
+  LES_ESTATE = -5,        /* call order violated (e.g. residual before metrics) */
+  LES_EUNSUPPORTED = -6   /* valid request this build does not provide */
+};
+
+enum les_precision {
+  LES_FP64 = 0,           /* state, metrics and fluxes in FP64 */
+  LES_FP32_STORAGE = 1    /* stage states, metrics, fluxes in FP32; Q^n and the
+                             RK accumulation Q^n - alpha dt R in FP64 */
+};
+
+enum les_bc {
+  LES_BC_PERIODIC = 0,    /* both faces of a direction; translation `period` */
+  LES_BC_AXIS = 1,        /* eta-: ghosts are the points across the axis
+                             (i, m, k + nth/2); needs even nth, zeta periodic */
+  LES_BC_INFLOW = 2,      /* xi-: entrance; target primitives from les_set_inflow */
+  LES_BC_OUTFLOW = 3,     /* xi+: exit with back pressure p_exit */
+  LES_BC_FARFIELD = 4     /* eta+: Riemann invariants with ref_prim */
+};
+
+enum les_sgs { LES_SGS_NONE = 0, LES_SGS_SMAGORINSKY = 1 };
+
+typedef struct les_params {
+  int32_t nx, nr, nth;        /* interior points along xi, eta, zeta (each >= 5) */
+  int32_t bc[6];              /* xi-, xi+, eta-, eta+, zeta-, zeta+ (enum les_bc) */
+  double period[3][3];        /* translation vector added across the periodic
+                                 faces of xi, eta, zeta (coordinates only) */
+  double gamma;               /* ratio of specific heats */
+  double Pr, Pr_sgs;          /* molecular and SGS Prandtl numbers */
+  double visc_coef;           /* M/Re factor of the viscous fluxes (0: inviscid) */
+  double suth_S;              /* Sutherland constant over the reference temperature */
+  double Cs;                  /* Smagorinsky constant */
+  double k2, k4;              /* dissipation constants */
+  double cfl;                 /* CFL number for the global time step */
+  double rk_alpha[5];         /* stage coefficients alpha_1..alpha_5 */
+  double ref_prim[5];         /* far-field state (rho, u, v, w, p) */
+  double p_exit;              /* exit back pressure */
+  int32_t sgs_model;          /* enum les_sgs */
+  int32_t precision;          /* enum les_precision */
+} les_params;
+
+/* ---- host-only helpers (no device work; callable without a GPU) -------- */
+
+/* Validate `p` (sizes >= 5, consistent boundary kinds, finite positive
+ * constants).  Returns LES_OK or LES_EINVAL. */
+int les_validate(const les_params* p);
+
+/* Padded layout for `p`: *pitch = row pitch in elements, dims[0..2] =
+ * (nth+4, nr+4, pitch), *var_stride = elements per variable.  Returns
+ * LES_EINVAL for invalid params, LES_EUNSUPPORTED if one variable exceeds
+ * 2^31 - 1 elements. */
+int les_layout(const les_params* p, int64_t* pitch, int64_t dims[3], int64_t* var_stride);
+
+/* Device bytes the context will hold (metrics + stage buffers + scratch). */
+int les_device_bytes(const les_params* p, size_t* bytes);
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context for the mesh `xyz` (device, FP64, shape (3, nth, nr, nx),
+ * coordinates x, y, z of the interior points, i fastest).  Ghost coordinates
+ * (three layers) are built on the device from the boundary kinds:
+ * periodic -> wrapped point plus `period`; axis -> point (i, m, k + nth/2);
+ * inflow/outflow/far field -> linear extrapolation in index space.
+ * The coordinates are copied; `xyz` may be freed after the call returns
+ * (the call synchronises `stream`).  Section "Transformation of
+ * Coordinates"; the centerline and periodic subsections of "Boundary
+ * Conditions". */
+int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, void* stream);
+
+/* Compute the metric terms J^-1 grad(xi), J^-1 grad(eta), J^-1 grad(zeta)
+ * and J^-1 on the padded box by central differences of the coordinates
+ * (metric-term and Jacobian equations of "Transformation of Coordinates";
+ * the eta row taken as the cofactor r_zeta x r_xi).  Frees the coordinates.
+ * If `metrics_out` (device, FP64, 10 padded variables in the order
+ * Sxi_x, Sxi_y, Sxi_z, Seta_x .. Szeta_z, V) is not NULL the FP64 metrics
+ * are copied there.  Must be called once before any residual. */
+int les_metrics(les_ctx* c, double* metrics_out, void* stream);
+
+/* Set the entrance target state: `prim_in` (device, FP64, shape (5, nth, nr),
+ * primitives rho, u, v, w, p per entrance point).  Copied.  Section
+ * "Entrance Boundary": a target with normal Mach >= 1 is imposed, otherwise
+ * Riemann invariants with the target as outside state.  Required when
+ * bc[0] == LES_BC_INFLOW. */
+int les_set_inflow(les_ctx* c, const double* prim_in, void* stream);
+
+/* Fill the ghost layers of Q (device, padded, 5 variables; FP64, or FP32 for
+ * LES_FP32_STORAGE) in place: xi faces on the interior of eta/zeta, then eta
+ * faces for all xi, then zeta faces everywhere (section "Boundary
+ * Conditions").  Used internally before every residual; exported for tests. */
+int les_fill_ghosts(les_ctx* c, void* Q, void* stream);
+
+/* Residual R(Q) (section "Spatial Discretization"): fills the ghosts of Q in
+ * place, then writes the interior of R (device, padded, 5 variables; FP64,
+ * or FP32 for LES_FP32_STORAGE).  Ghost entries of R are not written. */
+int les_residual(les_ctx* c, void* Q, void* R, void* stream);
+
+/* Advance Qn (device, FP64, padded, 5 variables) by `nsteps` Jameson RK5
+ * steps (section "Time Marching Method"):
+ *   Q^(0) = Q^n,  Q^(l) = Q^(0) - alpha_l dt R(Q^(l-1)),  Q^(n+1) = Q^(5),
+ * ghosts refilled before every residual.  dt_fixed > 0 uses that step;
+ * dt_fixed <= 0 takes dt = cfl / max over the interior of
+ * (lambda_xi + lambda_eta + lambda_zeta) of Q^n each step.  If `dt_out`
+ * (device, nsteps doubles) is not NULL the steps used are stored there.
+ * Synchronises `stream` once at the end to check the reductions; returns
+ * LES_ENONFINITE if one was not finite (Qn is then undefined). */
+int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed,
+                 double* dt_out, void* stream);
+
+/* Query the context: padded dims (nth+4, nr+4, pitch), variable stride in
+ * elements, and device bytes held. */
+int les_query(const les_ctx* c, int64_t dims[3], int64_t* var_stride, size_t* device_bytes);
+
+/* Message of the last failure on `c`, or of the calling thread when c is NULL
+ * (e.g. after les_init_grid failed).  Never NULL. */
+const char* les_last_error(const les_ctx* c);
+
+/* Release the context and its device memory (synchronises the device). */
+void les_free(les_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LESJET_H */

@@ -1,0 +1,426 @@
+// C-ABI of lesjet (declared in include/lesjet.h): argument validation,
+// context and device-memory ownership, and the RK5 driver that chains the
+// ghost fill, residual and stage-update kernels on the caller's stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lesjet.h"
+#include "launch.hpp"
+
+using namespace lesjet;
+
+struct les_ctx {
+  les_params p;
+  Grid g;
+  CGrid cg;
+  Phys<double> ph64;
+  Phys<float> ph32;
+  int device = 0;
+  double* coords = nullptr;    // padded coordinates (3 ghost layers), freed by les_metrics
+  void* M = nullptr;           // metrics, 10 padded variables of the storage type
+  double* inflow = nullptr;    // entrance target primitives (5, nth, nr)
+  void* stage[2] = {nullptr, nullptr};   // RK stage states (storage type)
+  void* R = nullptr;           // residual buffer (storage type)
+  void* PT = nullptr;          // point-quantity scratch of the two-pass residual
+  unsigned long long* maxbits = nullptr;
+  double* dt = nullptr;
+  int* flag = nullptr;
+  bool metrics_done = false;
+  bool inflow_set = false;
+  size_t bytes = 0;
+  std::string err;
+};
+
+static thread_local std::string t_err;
+
+static int fail(les_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  t_err = msg;
+  return code;
+}
+
+static int hip_fail(les_ctx* c, hipError_t e, const char* where) {
+  return fail(c, LES_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                                  \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #expr); \
+  } while (0)
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+static int validate(const les_params* p, std::string& why) {
+  if (!p) { why = "params is NULL"; return LES_EINVAL; }
+  if (p->nx < 5 || p->nr < 5 || p->nth < 5) { why = "each of nx, nr, nth must be >= 5"; return LES_EINVAL; }
+  const int* b = p->bc;
+  for (int f = 0; f < 6; ++f)
+    if (b[f] < LES_BC_PERIODIC || b[f] > LES_BC_FARFIELD) { why = "unknown boundary kind"; return LES_EINVAL; }
+  for (int d = 0; d < 3; ++d)
+    if ((b[2 * d] == LES_BC_PERIODIC) != (b[2 * d + 1] == LES_BC_PERIODIC)) {
+      why = "a periodic direction must be periodic on both faces";
+      return LES_EINVAL;
+    }
+  if (!(b[0] == LES_BC_PERIODIC || b[0] == LES_BC_INFLOW)) { why = "xi- must be periodic or inflow"; return LES_EINVAL; }
+  if (!(b[1] == LES_BC_PERIODIC || b[1] == LES_BC_OUTFLOW)) { why = "xi+ must be periodic or outflow"; return LES_EINVAL; }
+  if (!(b[2] == LES_BC_PERIODIC || b[2] == LES_BC_AXIS)) { why = "eta- must be periodic or axis"; return LES_EINVAL; }
+  if (!(b[3] == LES_BC_PERIODIC || b[3] == LES_BC_FARFIELD)) { why = "eta+ must be periodic or far field"; return LES_EINVAL; }
+  if (b[4] != LES_BC_PERIODIC || b[5] != LES_BC_PERIODIC) { why = "zeta must be periodic"; return LES_EINVAL; }
+  if (b[2] == LES_BC_AXIS && (p->nth % 2) != 0) { why = "the axis condition needs an even nth"; return LES_EINVAL; }
+  if (!(std::isfinite(p->gamma) && p->gamma > 1.0)) { why = "gamma must be > 1"; return LES_EINVAL; }
+  if (!finite_pos(p->Pr) || !finite_pos(p->Pr_sgs)) { why = "Prandtl numbers must be > 0"; return LES_EINVAL; }
+  if (!(std::isfinite(p->visc_coef) && p->visc_coef >= 0.0)) { why = "visc_coef must be >= 0"; return LES_EINVAL; }
+  if (!finite_pos(p->suth_S)) { why = "suth_S must be > 0"; return LES_EINVAL; }
+  if (!(std::isfinite(p->Cs) && p->Cs >= 0.0)) { why = "Cs must be >= 0"; return LES_EINVAL; }
+  if (!(std::isfinite(p->k2) && p->k2 >= 0.0 && std::isfinite(p->k4) && p->k4 >= 0.0)) { why = "k2, k4 must be >= 0"; return LES_EINVAL; }
+  if (!finite_pos(p->cfl)) { why = "cfl must be > 0"; return LES_EINVAL; }
+  for (int l = 0; l < 5; ++l)
+    if (!std::isfinite(p->rk_alpha[l])) { why = "rk_alpha must be finite"; return LES_EINVAL; }
+  for (int d = 0; d < 3; ++d)
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(p->period[d][c])) { why = "period must be finite"; return LES_EINVAL; }
+  if (b[3] == LES_BC_FARFIELD) {
+    for (int c = 0; c < 5; ++c)
+      if (!std::isfinite(p->ref_prim[c])) { why = "ref_prim must be finite"; return LES_EINVAL; }
+    if (!(p->ref_prim[0] > 0.0 && p->ref_prim[4] > 0.0)) { why = "ref_prim needs rho > 0 and p > 0"; return LES_EINVAL; }
+  }
+  if (b[1] == LES_BC_OUTFLOW && !finite_pos(p->p_exit)) { why = "p_exit must be > 0"; return LES_EINVAL; }
+  if (p->sgs_model != LES_SGS_NONE && p->sgs_model != LES_SGS_SMAGORINSKY) { why = "unknown sgs_model"; return LES_EINVAL; }
+  if (p->sgs_model == LES_SGS_SMAGORINSKY && p->visc_coef == 0.0 && p->Cs != 0.0) {
+    why = "the Smagorinsky model needs visc_coef > 0 (mu_sgs is in units of the jet viscosity)";
+    return LES_EINVAL;
+  }
+  if (p->precision != LES_FP64 && p->precision != LES_FP32_STORAGE) { why = "unknown precision"; return LES_EINVAL; }
+  return LES_OK;
+}
+
+static int make_layout(const les_params* p, Grid& g, CGrid& cg, std::string& why) {
+  const long long pitch = ((long long)p->nx + 2 * NG + 15) / 16 * 16;
+  const long long plane = pitch * (p->nr + 2 * NG);
+  const long long vs = plane * (p->nth + 2 * NG);
+  const long long cpitch = (long long)p->nx + 2 * NGC;
+  const long long cplane = cpitch * (p->nr + 2 * NGC);
+  const long long cvs = cplane * (p->nth + 2 * NGC);
+  if (vs > 2147483647LL || cvs > 2147483647LL) {
+    why = "one padded variable exceeds 2^31 - 1 elements";
+    return LES_EUNSUPPORTED;
+  }
+  g.nx = p->nx; g.nr = p->nr; g.nth = p->nth;
+  g.pitch = (int)pitch; g.plane = (int)plane; g.vs = (int)vs;
+  cg.nx = p->nx; cg.nr = p->nr; cg.nth = p->nth;
+  cg.pitch = (int)cpitch; cg.plane = (int)cplane; cg.vs = (int)cvs;
+  return LES_OK;
+}
+
+template <typename T>
+static Phys<T> make_phys(const les_params* p) {
+  Phys<T> ph;
+  ph.gamma = (T)p->gamma;
+  ph.gm1 = (T)(p->gamma - 1.0);
+  ph.igm1 = (T)(1.0 / (p->gamma - 1.0));
+  ph.Pr_inv = (T)(1.0 / p->Pr);
+  ph.Prs_inv = (T)(1.0 / p->Pr_sgs);
+  ph.Cv = (T)p->visc_coef;
+  ph.suth = (T)p->suth_S;
+  ph.suth1 = (T)(1.0 + p->suth_S);
+  ph.viscous = p->visc_coef != 0.0;
+  ph.sgs = ph.viscous && p->sgs_model == LES_SGS_SMAGORINSKY && p->Cs != 0.0;
+  ph.Cs2_over_Cv = ph.viscous ? (T)(p->Cs * p->Cs / p->visc_coef) : T(0);
+  ph.k2 = (T)p->k2;
+  ph.k4 = (T)p->k4;
+  for (int d = 0; d < 3; ++d)
+    for (int s = 0; s < 2; ++s) {
+      const int b = p->bc[2 * d + s];
+      ph.phys_face[d][s] = (b == LES_BC_INFLOW || b == LES_BC_OUTFLOW || b == LES_BC_FARFIELD);
+    }
+  return ph;
+}
+
+static size_t storage_size(const les_params* p) {
+  return p->precision == LES_FP32_STORAGE ? sizeof(float) : sizeof(double);
+}
+
+static void free_all(les_ctx* c) {
+  void* ptrs[] = {c->coords, c->M, c->inflow, c->stage[0], c->stage[1], c->R, c->PT,
+                  c->maxbits, c->dt, c->flag};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  c->coords = nullptr; c->M = nullptr; c->inflow = nullptr;
+  c->stage[0] = c->stage[1] = nullptr;
+  c->R = nullptr; c->PT = nullptr; c->maxbits = nullptr; c->dt = nullptr; c->flag = nullptr;
+}
+
+static int dalloc(les_ctx* c, void** ptr, size_t bytes, const char* what) {
+  if (*ptr) return LES_OK;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(c, LES_ENOMEM, std::string("device allocation of ") + what + " (" +
+                                   std::to_string(bytes) + " bytes) failed: " + hipGetErrorString(e));
+  }
+  c->bytes += bytes;
+  return LES_OK;
+}
+
+// The exported functions below take C linkage from their declarations in
+// lesjet.h.
+
+int les_validate(const les_params* p) {
+  std::string why;
+  const int r = validate(p, why);
+  return r == LES_OK ? r : fail(nullptr, r, why);
+}
+
+int les_layout(const les_params* p, int64_t* pitch, int64_t dims[3], int64_t* var_stride) {
+  std::string why;
+  int r = validate(p, why);
+  if (r != LES_OK) return fail(nullptr, r, why);
+  Grid g;
+  CGrid cg;
+  r = make_layout(p, g, cg, why);
+  if (r != LES_OK) return fail(nullptr, r, why);
+  if (pitch) *pitch = g.pitch;
+  if (dims) { dims[0] = p->nth + 2 * NG; dims[1] = p->nr + 2 * NG; dims[2] = g.pitch; }
+  if (var_stride) *var_stride = g.vs;
+  return LES_OK;
+}
+
+int les_device_bytes(const les_params* p, size_t* bytes) {
+  std::string why;
+  int r = validate(p, why);
+  if (r != LES_OK) return fail(nullptr, r, why);
+  if (!bytes) return fail(nullptr, LES_EINVAL, "bytes is NULL");
+  Grid g;
+  CGrid cg;
+  r = make_layout(p, g, cg, why);
+  if (r != LES_OK) return fail(nullptr, r, why);
+  const size_t ts = storage_size(p);
+  // metrics + two stage states + residual + point scratch
+  *bytes = (size_t)g.vs * ts * (10 + 5 + 5 + 5 + 21) + (size_t)5 * p->nth * p->nr * sizeof(double);
+  return LES_OK;
+}
+
+int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, void* stream) {
+  if (!out) return fail(nullptr, LES_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  int r = validate(p, why);
+  if (r != LES_OK) return fail(nullptr, r, why);
+  if (!xyz) return fail(nullptr, LES_EINVAL, "xyz is NULL");
+  les_ctx* c = new (std::nothrow) les_ctx();
+  if (!c) return fail(nullptr, LES_ENOMEM, "host allocation failed");
+  c->p = *p;
+  r = make_layout(p, c->g, c->cg, why);
+  if (r != LES_OK) { delete c; return fail(nullptr, r, why); }
+  c->ph64 = make_phys<double>(p);
+  c->ph32 = make_phys<float>(p);
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipGetDevice"); }
+  hipStream_t s = (hipStream_t)stream;
+  r = dalloc(c, (void**)&c->coords, (size_t)3 * c->cg.vs * sizeof(double), "coordinates");
+  if (r == LES_OK) r = dalloc(c, (void**)&c->maxbits, sizeof(unsigned long long), "reduction slot");
+  if (r == LES_OK) r = dalloc(c, (void**)&c->dt, sizeof(double), "dt");
+  if (r == LES_OK) r = dalloc(c, (void**)&c->flag, sizeof(int), "flag");
+  if (r != LES_OK) { t_err = c->err; free_all(c); delete c; return r; }
+  e = launch_coords(xyz, c->coords, c->cg, p->bc, p->period, s);
+  if (e == hipSuccess) e = launch_reset(c->maxbits, c->flag, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    hip_fail(nullptr, e, "les_init_grid");
+    free_all(c);
+    delete c;
+    return LES_EHIP;
+  }
+  *out = c;
+  return LES_OK;
+}
+
+int les_metrics(les_ctx* c, double* metrics_out, void* stream) {
+  if (!c) return fail(nullptr, LES_EINVAL, "ctx is NULL");
+  if (c->metrics_done) return fail(c, LES_ESTATE, "metrics already computed");
+  if (!c->coords) return fail(c, LES_ESTATE, "no coordinates");
+  hipStream_t s = (hipStream_t)stream;
+  int r = dalloc(c, &c->M, (size_t)10 * c->g.vs * storage_size(&c->p), "metrics");
+  if (r != LES_OK) return r;
+  hipError_t e;
+  if (c->p.precision == LES_FP32_STORAGE)
+    e = launch_metrics<float>(c->coords, c->cg, (float*)c->M, c->g, metrics_out, s);
+  else
+    e = launch_metrics<double>(c->coords, c->cg, (double*)c->M, c->g, metrics_out, s);
+  if (e != hipSuccess) return hip_fail(c, e, "metrics kernel");
+  HIP_TRY(c, hipStreamSynchronize(s));
+  HIP_TRY(c, hipFree(c->coords));
+  c->bytes -= (size_t)3 * c->cg.vs * sizeof(double);
+  c->coords = nullptr;
+  c->metrics_done = true;
+  return LES_OK;
+}
+
+int les_set_inflow(les_ctx* c, const double* prim_in, void* stream) {
+  if (!c) return fail(nullptr, LES_EINVAL, "ctx is NULL");
+  if (!prim_in) return fail(c, LES_EINVAL, "prim_in is NULL");
+  const size_t bytes = (size_t)5 * c->p.nth * c->p.nr * sizeof(double);
+  int r = dalloc(c, (void**)&c->inflow, bytes, "inflow data");
+  if (r != LES_OK) return r;
+  HIP_TRY(c, hipMemcpyAsync(c->inflow, prim_in, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  c->inflow_set = true;
+  return LES_OK;
+}
+
+static int ready(les_ctx* c) {
+  if (!c) return fail(nullptr, LES_EINVAL, "ctx is NULL");
+  if (!c->metrics_done) return fail(c, LES_ESTATE, "les_metrics has not been called");
+  if (c->p.bc[0] == LES_BC_INFLOW && !c->inflow_set)
+    return fail(c, LES_ESTATE, "les_set_inflow has not been called");
+  return LES_OK;
+}
+
+template <typename T>
+static hipError_t ghosts(les_ctx* c, T* Q, hipStream_t s);
+
+template <>
+hipError_t ghosts<double>(les_ctx* c, double* Q, hipStream_t s) {
+  return launch_ghosts<double>(Q, c->g, (const double*)c->M, c->inflow, c->ph64, c->p.bc,
+                               c->p.ref_prim, c->p.p_exit, s);
+}
+template <>
+hipError_t ghosts<float>(les_ctx* c, float* Q, hipStream_t s) {
+  return launch_ghosts<float>(Q, c->g, (const float*)c->M, c->inflow, c->ph32, c->p.bc,
+                              c->p.ref_prim, c->p.p_exit, s);
+}
+
+template <typename T>
+static const Phys<T>& phys(les_ctx* c);
+template <>
+const Phys<double>& phys<double>(les_ctx* c) { return c->ph64; }
+template <>
+const Phys<float>& phys<float>(les_ctx* c) { return c->ph32; }
+
+// R(Q) into R_out (ghosts of Q filled first).
+template <typename T>
+static int residual_into(les_ctx* c, T* Q, T* R_out, hipStream_t s) {
+  int r = dalloc(c, &c->PT, (size_t)21 * c->g.vs * sizeof(T), "point scratch");
+  if (r != LES_OK) return r;
+  hipError_t e = ghosts<T>(c, Q, s);
+  if (e == hipSuccess)
+    e = launch_residual_ref<T>(Q, (const T*)c->M, c->g, phys<T>(c), (T*)c->PT, R_out, s);
+  if (e != hipSuccess) return hip_fail(c, e, "residual kernels");
+  return LES_OK;
+}
+
+int les_fill_ghosts(les_ctx* c, void* Q, void* stream) {
+  int r = ready(c);
+  if (r != LES_OK) return r;
+  if (!Q) return fail(c, LES_EINVAL, "Q is NULL");
+  hipError_t e = c->p.precision == LES_FP32_STORAGE
+                     ? ghosts<float>(c, (float*)Q, (hipStream_t)stream)
+                     : ghosts<double>(c, (double*)Q, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "ghost kernels");
+  return LES_OK;
+}
+
+int les_residual(les_ctx* c, void* Q, void* R, void* stream) {
+  int r = ready(c);
+  if (r != LES_OK) return r;
+  if (!Q || !R) return fail(c, LES_EINVAL, "Q or R is NULL");
+  if (Q == R) return fail(c, LES_EINVAL, "Q and R must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  if (c->p.precision == LES_FP32_STORAGE) return residual_into<float>(c, (float*)Q, (float*)R, s);
+  return residual_into<double>(c, (double*)Q, (double*)R, s);
+}
+
+template <typename T>
+static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double* dt_out,
+                     hipStream_t s) {
+  const size_t fb = (size_t)5 * c->g.vs * sizeof(T);
+  int r = dalloc(c, &c->stage[0], fb, "stage state");
+  if (r == LES_OK) r = dalloc(c, &c->stage[1], fb, "stage state");
+  if (r == LES_OK) r = dalloc(c, &c->R, fb, "residual");
+  if (r != LES_OK) return r;
+  const bool fp32 = sizeof(T) == sizeof(float);
+  T* S0 = (T*)c->stage[0];
+  T* S1 = (T*)c->stage[1];
+  hipError_t e = launch_reset(c->maxbits, c->flag, s);
+  // FP32 storage: the stage-0 state is an FP32 copy of Q^n
+  T* cur = (T*)Qn;
+  if (fp32 && e == hipSuccess) {
+    e = launch_to_float(Qn, (float*)S1, (long long)5 * c->g.vs, s);
+    cur = S1;
+  }
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+    e = ghosts<T>(c, cur, s);
+    if (e == hipSuccess && dt_fixed <= 0.0) {
+      if (fp32) e = launch_lambda_max<double, float>(Qn, (const float*)c->M, c->g, c->ph64, c->maxbits, s);
+      else e = launch_lambda_max<double, double>(Qn, (const double*)c->M, c->g, c->ph64, c->maxbits, s);
+    }
+    if (e == hipSuccess)
+      e = launch_dt_finalize(c->maxbits, c->p.cfl, dt_fixed, c->dt, dt_out ? dt_out + n : nullptr,
+                             c->flag, s);
+    T* src = cur;
+    for (int l = 0; l < 5 && e == hipSuccess; ++l) {
+      if (l > 0) e = ghosts<T>(c, src, s);
+      if (e != hipSuccess) break;
+      e = launch_residual_ref<T>(src, (const T*)c->M, c->g, phys<T>(c), (T*)c->PT, (T*)c->R, s);
+      if (e != hipSuccess) break;
+      T* dst;
+      if (l < 4) {
+        dst = (src == S0) ? S1 : S0;
+        e = launch_rk_update<T, T>(Qn, (const T*)c->R, dst, nullptr, c->g, c->p.rk_alpha[l], c->dt, s);
+      } else if (!fp32) {
+        dst = (T*)Qn;
+        e = launch_rk_update<T, T>(Qn, (const T*)c->R, dst, nullptr, c->g, c->p.rk_alpha[l], c->dt, s);
+      } else {
+        // Q^(n+1) in FP64 and its FP32 copy for the next step
+        dst = (src == S0) ? S1 : S0;
+        e = launch_rk_update<T, T>(Qn, (const T*)c->R, dst, Qn, c->g, c->p.rk_alpha[l], c->dt, s);
+      }
+      src = dst;
+    }
+    cur = src;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "rk5 kernels");
+  int flag = 0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (flag) return fail(c, LES_ENONFINITE, "time-step reduction was not finite (state diverged)");
+  return LES_OK;
+}
+
+int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed, double* dt_out,
+                 void* stream) {
+  int r = ready(c);
+  if (r != LES_OK) return r;
+  if (!Qn) return fail(c, LES_EINVAL, "Qn is NULL");
+  if (nsteps < 0) return fail(c, LES_EINVAL, "nsteps must be >= 0");
+  if (!std::isfinite(dt_fixed)) return fail(c, LES_EINVAL, "dt_fixed must be finite");
+  if (nsteps == 0) return LES_OK;
+  hipStream_t s = (hipStream_t)stream;
+  r = dalloc(c, &c->PT, (size_t)21 * c->g.vs * storage_size(&c->p), "point scratch");
+  if (r != LES_OK) return r;
+  if (c->p.precision == LES_FP32_STORAGE) return rk5_steps<float>(c, Qn, nsteps, dt_fixed, dt_out, s);
+  return rk5_steps<double>(c, Qn, nsteps, dt_fixed, dt_out, s);
+}
+
+int les_query(const les_ctx* c, int64_t dims[3], int64_t* var_stride, size_t* device_bytes) {
+  if (!c) return fail(nullptr, LES_EINVAL, "ctx is NULL");
+  if (dims) { dims[0] = c->p.nth + 2 * NG; dims[1] = c->p.nr + 2 * NG; dims[2] = c->g.pitch; }
+  if (var_stride) *var_stride = c->g.vs;
+  if (device_bytes) *device_bytes = c->bytes;
+  return LES_OK;
+}
+
+const char* les_last_error(const les_ctx* c) {
+  return c ? c->err.c_str() : t_err.c_str();
+}
+
+void les_free(les_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+}

@@ -1,0 +1,39 @@
+// Host-side launchers of the lesjet kernels (one translation unit per
+// subsystem; the C-ABI in api.cpp calls these).
+#pragma once
+
+#include "common.hpp"
+
+namespace lesjet {
+
+hipError_t launch_coords(const double* xyz, double* C, const CGrid& cg, const int bc[6],
+                         const double period[3][3], hipStream_t s);
+
+template <typename T>
+hipError_t launch_metrics(const double* C, const CGrid& cg, T* M, const Grid& g, double* M64,
+                          hipStream_t s);
+
+template <typename T>
+hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow, const Phys<T>& ph,
+                         const int bc[6], const double ref_prim[5], double p_exit, hipStream_t s);
+
+template <typename T>
+hipError_t launch_residual_ref(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, T* PT,
+                               T* R, hipStream_t s);
+
+template <typename TQ, typename TM>
+hipError_t launch_lambda_max(const TQ* Q, const TM* M, const Grid& g, const Phys<double>& ph,
+                             unsigned long long* maxbits, hipStream_t s);
+
+hipError_t launch_dt_finalize(unsigned long long* maxbits, double cfl, double dt_fixed,
+                              double* dt, double* dt_out, int* flag, hipStream_t s);
+
+hipError_t launch_reset(unsigned long long* maxbits, int* flag, hipStream_t s);
+
+template <typename T, typename TS>
+hipError_t launch_rk_update(const double* Q0, const T* R, TS* Qout, double* Q64out, const Grid& g,
+                            double alpha, const double* dt, hipStream_t s);
+
+hipError_t launch_to_float(const double* a, float* b, long long n, hipStream_t s);
+
+}  // namespace lesjet

@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/lesjet.h declares, and the host-only entry points validate
+arguments before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from cases import problems
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lesjet.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(les_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("les_init_grid", "les_metrics", "les_residual", "les_rk5_step"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2301_00817_amd import binding
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(binding.EXPORTS) <= set(_declared())
+
+
+def _params(**over):
+    from paper_2301_00817_amd import binding as B
+    pb = problems.jet_params()
+    pb.update(over)
+    return B.make_params(pb, (288, 160, 128))
+
+
+def test_validate_and_layout_host_only():
+    from paper_2301_00817_amd import binding as B
+    p = _params()
+    assert B.les_validate(p) == 0
+    pitch, dims, vs = B.les_layout(p)
+    assert pitch % 16 == 0 and pitch >= 288 + 4
+    assert dims == (128 + 4, 160 + 4, pitch)
+    assert vs == dims[0] * dims[1] * dims[2]
+    assert B.les_device_bytes(p) > 10 * vs * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=4), dict(nth=7), dict(gamma=1.0), dict(cfl=0.0), dict(Pr=-1.0),
+    dict(bc=(2, 0, 1, 4, 0, 0)),            # inflow with periodic xi+
+    dict(bc=(2, 3, 1, 4, 2, 3)),            # zeta not periodic
+    dict(sgs_model=7), dict(precision=3), dict(p_exit=0.0),
+])
+def test_validate_rejects(bad):
+    from paper_2301_00817_amd import binding as B
+    prm = problems.jet_params()
+    shape = [288, 160, 128]
+    prec = 0
+    for k, v in bad.items():
+        if k in ("nx", "nr", "nth"):
+            shape[("nx", "nr", "nth").index(k)] = v
+        elif k == "precision":
+            prec = v
+        else:
+            prm[k] = v
+    p = B.make_params(prm, shape, prec)
+    with pytest.raises(B.LesError) as e:
+        B.les_validate(p)
+    assert e.value.code == B.LES_EINVAL
+    assert B.les_last_error(None)
+
+
+def test_layout_refuses_oversized_variable():
+    from paper_2301_00817_amd import binding as B
+    p = _params()
+    p.nx, p.nr, p.nth = 2000, 2000, 1000
+    with pytest.raises(B.LesError) as e:
+        B.les_layout(p)
+    assert e.value.code == B.LES_EUNSUPPORTED
+
+
+def test_init_grid_rejects_null_before_device_work():
+    from paper_2301_00817_amd import binding as B
+    with pytest.raises(B.LesError) as e:
+        B.les_init_grid(_params(), None)
+    assert e.value.code == B.LES_EINVAL
+
+
+def test_big_mesh_layout_fits_32bit_offsets():
+    """The 1250 x 640 x 1250 mesh: one padded variable stays below 2^31
+    elements, so per-variable offsets are 32-bit."""
+    from paper_2301_00817_amd import binding as B
+    p = _params()
+    p.nx, p.nr, p.nth = 1250, 640, 1250
+    pitch, dims, vs = B.les_layout(p)
+    assert vs < 2 ** 31
+    assert 5 * vs > 2 ** 32          # whole fields need 64-bit bases

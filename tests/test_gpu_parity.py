@@ -1,0 +1,180 @@
+"""GPU parity of the plain FP64 path against the CPU oracle, through the
+C-ABI: metrics, ghost fill, residual, time step and RK5 steps, on grids that
+span several tiles with ragged tails, plus properties at full size.
+
+Bars (FP64): metrics and copied ghosts agree to rounding (1e-14 relative);
+the residual to 1e-12 of its max per group (mass, momentum, energy); the
+state after 10 RK5 steps to 1e-11.  The GPU contracts multiply-adds and
+uses reciprocal multiplies where the oracle divides, so agreement is to a
+few ulps of the flux scale, amplified by the cancellation in flux
+differences."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from _helpers import announce, grouped_rel_err, make_solver, to_np
+from cases import problems
+from oracle import les
+
+pytestmark = pytest.mark.gpu
+
+R_BAR = 1e-12
+Q_BAR = 1e-11
+
+
+def _oracle(pb):
+    xyz = pb["xyz"].numpy()
+    geo = les.geometry(xyz, pb["params"])
+    inflow = pb["inflow"].numpy() if pb.get("inflow") is not None else None
+    return geo, inflow
+
+
+def _jet(nx, nr, nth, perturb=0.0, seed=2):
+    pb = problems.jet_problem(nx, nr, nth, seed=seed)
+    if perturb:
+        Q = pb["Q"].clone()
+        g = torch.Generator().manual_seed(7)
+        Q[1:4] += perturb * torch.randn(Q[1:4].shape, generator=g, dtype=torch.float64)
+        pb["Q"] = Q
+    return pb
+
+
+CASES = {
+    "box32": lambda: problems.box_problem(32),
+    "box32_cs018": lambda: problems.box_problem(32, Cs=0.18),
+    "box_ragged": lambda: problems.box_problem(17, shape=(17, 23, 9)),
+    "jet8x6x8": lambda: _jet(8, 6, 8, perturb=0.05),
+    "jet37x22x20": lambda: _jet(37, 22, 20),
+    "jet70x33x24": lambda: _jet(70, 33, 24, perturb=0.01),
+}
+
+
+@pytest.mark.parametrize("name", ["box32", "jet37x22x20", "jet70x33x24"])
+def test_metrics_match_oracle(name):
+    announce("metrics", name)
+    pb = CASES[name]()
+    geo, _ = _oracle(pb)
+    s = make_solver(pb, keep_metrics=True)
+    M = to_np(s.metrics64)[..., :s.shape[0] + 4]
+    S = geo["S"].reshape(9, *geo["V"].shape)
+    assert np.abs(M[:9] - S).max() <= 1e-14 * np.abs(S).max()
+    assert np.abs(M[9] - geo["V"]).max() <= 1e-14 * np.abs(geo["V"]).max()
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["box_ragged", "jet8x6x8", "jet37x22x20"])
+def test_ghost_fill_matches_oracle_and_defines_every_point(name):
+    """Ghosts poisoned with NaN before the fill: every padded point must be
+    finite afterwards; copies bitwise, Riemann states to rounding."""
+    announce("ghosts", name)
+    pb = CASES[name]()
+    geo, inflow = _oracle(pb)
+    Qp = les.pad_state(pb["Q"].numpy())
+    les.fill_ghosts(Qp, geo, pb["params"], inflow)
+    s = make_solver(pb)
+    G = s.pad(pb["Q"].cuda())
+    s.fill_ghosts(G)
+    torch.cuda.synchronize()
+    Gn = to_np(G)[..., :s.shape[0] + 4]
+    assert np.isfinite(Gn).all()
+    assert grouped_rel_err(Gn, Qp) <= 1e-14
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_matches_oracle(name):
+    announce("residual", name)
+    pb = CASES[name]()
+    geo, inflow = _oracle(pb)
+    R_ref = les.evaluate(pb["Q"].numpy(), geo, pb["params"], inflow)
+    s = make_solver(pb)
+    Qp = s.pad(pb["Q"].cuda())
+    R = to_np(s.interior(s.residual(Qp)))
+    assert np.isfinite(R).all()
+    err = grouped_rel_err(R, R_ref)
+    print(f"{name}: residual rel err {err:.3e}")
+    assert err <= R_BAR
+    s.close()
+
+
+def test_time_step_matches_oracle():
+    announce("dt", "jet37x22x20")
+    pb = CASES["jet37x22x20"]()
+    geo, inflow = _oracle(pb)
+    dt_ref = les.time_step(pb["Q"].numpy(), geo, pb["params"])
+    s = make_solver(pb)
+    Qn = s.pad(pb["Q"].cuda(), dtype=torch.float64)
+    dt = float(s.rk5_step(Qn, 1)[0])
+    assert abs(dt - dt_ref) <= 1e-14 * dt_ref
+    s.close()
+
+
+@pytest.mark.parametrize("name,steps", [("box32", 10), ("jet37x22x20", 10), ("jet8x6x8", 4)])
+def test_rk5_steps_match_oracle(name, steps):
+    announce("rk5", name, steps)
+    pb = CASES[name]()
+    geo, inflow = _oracle(pb)
+    Q_ref, dts = les.run(pb["Q"].numpy(), geo, pb["params"], inflow, steps=steps)
+    s = make_solver(pb)
+    Qn = s.pad(pb["Q"].cuda(), dtype=torch.float64)
+    dt = to_np(s.rk5_step(Qn, steps))
+    Q = to_np(s.interior(Qn))
+    assert np.allclose(dt, dts, rtol=1e-12, atol=0)
+    err = grouped_rel_err(Q, Q_ref)
+    print(f"{name}: Q after {steps} steps rel err {err:.3e}")
+    assert err <= Q_BAR
+    s.close()
+
+
+def test_rk5_fixed_dt_and_reproducible():
+    """Fixed dt is used as given; two runs from the same state are bitwise
+    equal (no atomics on floats, fixed summation order)."""
+    announce("rk5-repro", "jet37x22x20")
+    pb = CASES["jet37x22x20"]()
+    s = make_solver(pb)
+    out = []
+    for _ in range(2):
+        Qn = s.pad(pb["Q"].cuda(), dtype=torch.float64)
+        dt = s.rk5_step(Qn, 3, dt=1e-4)
+        out.append(to_np(s.interior(Qn)))
+    assert np.all(to_np(dt) == 1e-4)
+    assert np.array_equal(out[0], out[1])
+    s.close()
+
+
+def test_residual_2M_jet_matches_oracle():
+    """The 160 x 100 x 128 jet mesh (2.05 M points), full comparison."""
+    announce("residual", "jet160x100x128")
+    pb = problems.jet_problem(160, 100, 128, seed=4)
+    geo, inflow = _oracle(pb)
+    R_ref = les.evaluate(pb["Q"].numpy(), geo, pb["params"], inflow)
+    s = make_solver(pb)
+    Qp = s.pad(pb["Q"].cuda())
+    R = to_np(s.interior(s.residual(Qp)))
+    err = grouped_rel_err(R, R_ref)
+    print(f"2M: residual rel err {err:.3e}")
+    assert err <= R_BAR
+    s.close()
+
+
+def test_free_stream_on_5p9M_jet_mesh():
+    """Full-size 288 x 160 x 128 mesh: a uniform state (boundary data equal
+    to it) keeps a residual at rounding level, max |V R| / max |F| <= 1e-12."""
+    announce("free-stream", "jet288x160x128")
+    prim = (1.0, 0.6, 0.3, -0.2, 1.0 / 1.4)
+    pb = problems.jet_problem(288, 160, 128, noise=0.0)
+    pb["params"] = dict(pb["params"], ref_prim=prim, p_exit=prim[4])
+    pb["inflow"] = torch.tensor(prim, dtype=torch.float64).view(5, 1, 1).expand(5, 128, 160).contiguous()
+    from cases import flow
+    Q = flow.uniform_state((128, 160, 288), prim)
+    s = make_solver(pb, keep_metrics=True)
+    Qp = s.pad(Q.cuda())
+    R = s.interior(s.residual(Qp))
+    V = s.interior(s.metrics64[9:10])
+    VR = float((R * V).abs().max())
+    Smax = float(s.metrics64[:9].abs().max())
+    fscale = Smax * (prim[0] * 0.6 ** 2 + prim[4])
+    assert VR <= 1e-12 * fscale
+    s.close()

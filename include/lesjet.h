@@ -121,7 +121,10 @@ int les_device_bytes(const les_params* p, size_t* bytes);
  * periodic -> wrapped point plus `period`; axis -> point (i, m, k + nth/2);
  * inflow/outflow/far field -> linear extrapolation in index space.
  * The coordinates are copied; `xyz` may be freed after the call returns
- * (the call synchronises `stream`).  Section "Transformation of
+ * (the call synchronises `stream`).  The environment variable LESJET_KCHUNK,
+ * if set to a positive integer, overrides the number of azimuthal planes
+ * one block of the fused kernel marches over (tuning and tests).
+ * Section "Transformation of
  * Coordinates"; the centerline and periodic subsections of "Boundary
  * Conditions". */
 int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, void* stream);
@@ -153,6 +156,12 @@ int les_fill_ghosts(les_ctx* c, void* Q, void* stream);
  * or FP32 for LES_FP32_STORAGE).  Ghost entries of R are not written. */
 int les_residual(les_ctx* c, void* Q, void* R, void* stream);
 
+/* The same residual computed by the two-pass reference kernels (a point
+ * pass storing the point quantities of every point in library scratch, then
+ * a face pass): simple indexing, several times the memory traffic.  For
+ * validating the fused kernel on meshes the CPU oracle cannot handle. */
+int les_residual_reference(les_ctx* c, void* Q, void* R, void* stream);
+
 /* Advance Qn (device, FP64, padded, 5 variables) by `nsteps` Jameson RK5
  * steps (section "Time Marching Method"):
  *   Q^(0) = Q^n,  Q^(l) = Q^(0) - alpha_l dt R(Q^(l-1)),  Q^(n+1) = Q^(5),
@@ -164,6 +173,15 @@ int les_residual(les_ctx* c, void* Q, void* R, void* stream);
  * LES_ENONFINITE if one was not finite (Qn is then undefined). */
 int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed,
                  double* dt_out, void* stream);
+
+/* Measurement support.  While enabled, every launch of the residual stage
+ * kernel issued by les_residual and les_rk5_step is bracketed by a pair of
+ * HIP events recorded on the call's stream, so the durations are those of
+ * that kernel alone.  les_profile_read synchronises the recorded events,
+ * returns the number of launches and their summed duration in milliseconds,
+ * and clears the record.  Off by default (no events are recorded). */
+int les_profile(les_ctx* c, int32_t enable);
+int les_profile_read(les_ctx* c, int64_t* launches, double* total_ms);
 
 /* Query the context: padded dims (nth+4, nr+4, pitch), variable stride in
  * elements, and device bytes held. */

@@ -77,7 +77,10 @@ def _load():
         "les_set_inflow": ([vp, vp, vp], ctypes.c_int),
         "les_fill_ghosts": ([vp, vp, vp], ctypes.c_int),
         "les_residual": ([vp, vp, vp, vp], ctypes.c_int),
+        "les_residual_reference": ([vp, vp, vp, vp], ctypes.c_int),
         "les_rk5_step": ([vp, vp, i32, dbl, vp, vp], ctypes.c_int),
+        "les_profile": ([vp, i32], ctypes.c_int),
+        "les_profile_read": ([vp, P(i64), P(dbl)], ctypes.c_int),
         "les_query": ([vp, P(i64 * 3), P(i64), P(sz)], ctypes.c_int),
         "les_last_error": ([vp], ctypes.c_char_p),
         "les_free": ([vp], None),
@@ -91,7 +94,9 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("les_validate", "les_layout", "les_device_bytes", "les_init_grid", "les_metrics",
-           "les_set_inflow", "les_fill_ghosts", "les_residual", "les_rk5_step", "les_query",
+           "les_set_inflow", "les_fill_ghosts", "les_residual", "les_residual_reference",
+           "les_rk5_step", "les_profile",
+           "les_profile_read", "les_query",
            "les_last_error", "les_free")
 
 
@@ -144,8 +149,22 @@ def les_residual(ctx, q_ptr, r_ptr, stream=0):
     return _check(_lib.les_residual(ctx, q_ptr, r_ptr, stream), ctx)
 
 
+def les_residual_reference(ctx, q_ptr, r_ptr, stream=0):
+    return _check(_lib.les_residual_reference(ctx, q_ptr, r_ptr, stream), ctx)
+
+
 def les_rk5_step(ctx, qn_ptr, nsteps, dt_fixed=0.0, dt_out_ptr=None, stream=0):
     return _check(_lib.les_rk5_step(ctx, qn_ptr, int(nsteps), float(dt_fixed), dt_out_ptr, stream), ctx)
+
+
+def les_profile(ctx, enable):
+    return _check(_lib.les_profile(ctx, int(bool(enable))), ctx)
+
+
+def les_profile_read(ctx):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(_lib.les_profile_read(ctx, ctypes.byref(n), ctypes.byref(ms)), ctx)
+    return n.value, ms.value
 
 
 def les_query(ctx):

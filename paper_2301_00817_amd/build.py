@@ -20,7 +20,8 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "liblesjet.so")
 ARCH = os.environ.get("LESJET_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "geometry.hip", "ghost.hip", "residual_ref.hip", "rk.hip"]
+SOURCES = ["api.cpp", "geometry.hip", "ghost.hip", "residual_ref.hip", "residual_fused.hip",
+           "rk.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -3,9 +3,11 @@
 // ghost fill, residual and stage-update kernels on the caller's stream.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lesjet.h"
 #include "launch.hpp"
@@ -19,6 +21,8 @@ struct les_ctx {
   Phys<double> ph64;
   Phys<float> ph32;
   int device = 0;
+  int num_cu = 256;
+  int kc = 16;                 // k-chunk of the fused kernel
   double* coords = nullptr;    // padded coordinates (3 ghost layers), freed by les_metrics
   void* M = nullptr;           // metrics, 10 padded variables of the storage type
   double* inflow = nullptr;    // entrance target primitives (5, nth, nr)
@@ -32,7 +36,30 @@ struct les_ctx {
   bool inflow_set = false;
   size_t bytes = 0;
   std::string err;
+  // kernel timing (les_profile)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  size_t ev_used = 0;           // pairs recorded since the last read
 };
+
+// Record the start event of a timed launch; returns the pair index or -1.
+static long prof_begin(les_ctx* c, hipStream_t s) {
+  if (!c->prof) return -1;
+  if (2 * (c->ev_used + 1) > c->ev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return -1; }
+    c->ev.push_back(a);
+    c->ev.push_back(b);
+  }
+  const long k = (long)c->ev_used++;
+  if (hipEventRecord(c->ev[2 * k], s) != hipSuccess) { --c->ev_used; return -1; }
+  return k;
+}
+
+static void prof_end(les_ctx* c, long k, hipStream_t s) {
+  if (k >= 0) (void)hipEventRecord(c->ev[2 * k + 1], s);
+}
 
 static thread_local std::string t_err;
 
@@ -200,8 +227,9 @@ int les_device_bytes(const les_params* p, size_t* bytes) {
   r = make_layout(p, g, cg, why);
   if (r != LES_OK) return fail(nullptr, r, why);
   const size_t ts = storage_size(p);
-  // metrics + two stage states + residual + point scratch
-  *bytes = (size_t)g.vs * ts * (10 + 5 + 5 + 5 + 21) + (size_t)5 * p->nth * p->nr * sizeof(double);
+  // metrics + two stage states (the two-pass reference form adds 21 scratch
+  // variables when it is used)
+  *bytes = (size_t)g.vs * ts * (10 + 5 + 5) + (size_t)5 * p->nth * p->nr * sizeof(double);
   return LES_OK;
 }
 
@@ -221,6 +249,13 @@ int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, void* s
   c->ph32 = make_phys<float>(p);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipGetDevice"); }
+  e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipDeviceGetAttribute"); }
+  c->kc = fused_chunk(c->g, c->num_cu);
+  if (const char* kc = std::getenv("LESJET_KCHUNK")) {   // tuning / test override
+    const int v = std::atoi(kc);
+    if (v >= 1) c->kc = v;
+  }
   hipStream_t s = (hipStream_t)stream;
   r = dalloc(c, (void**)&c->coords, (size_t)3 * c->cg.vs * sizeof(double), "coordinates");
   if (r == LES_OK) r = dalloc(c, (void**)&c->maxbits, sizeof(unsigned long long), "reduction slot");
@@ -301,15 +336,29 @@ const Phys<double>& phys<double>(les_ctx* c) { return c->ph64; }
 template <>
 const Phys<float>& phys<float>(les_ctx* c) { return c->ph32; }
 
-// R(Q) into R_out (ghosts of Q filled first).
+// R(Q) into R_out (ghosts of Q filled first), fused kernel.
 template <typename T>
 static int residual_into(les_ctx* c, T* Q, T* R_out, hipStream_t s) {
+  hipError_t e = ghosts<T>(c, Q, s);
+  if (e == hipSuccess) {
+    const long k = prof_begin(c, s);
+    e = launch_fused<T>(Q, (const T*)c->M, c->g, phys<T>(c), c->kc, FUSED_EPI_R, R_out, nullptr,
+                        nullptr, 0.0, nullptr, c->ph64, nullptr, s);
+    prof_end(c, k, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "residual kernel");
+  return LES_OK;
+}
+
+// Same, with the two-pass reference kernels.
+template <typename T>
+static int residual_ref_into(les_ctx* c, T* Q, T* R_out, hipStream_t s) {
   int r = dalloc(c, &c->PT, (size_t)21 * c->g.vs * sizeof(T), "point scratch");
   if (r != LES_OK) return r;
   hipError_t e = ghosts<T>(c, Q, s);
   if (e == hipSuccess)
     e = launch_residual_ref<T>(Q, (const T*)c->M, c->g, phys<T>(c), (T*)c->PT, R_out, s);
-  if (e != hipSuccess) return hip_fail(c, e, "residual kernels");
+  if (e != hipSuccess) return hip_fail(c, e, "reference residual kernels");
   return LES_OK;
 }
 
@@ -322,6 +371,16 @@ int les_fill_ghosts(les_ctx* c, void* Q, void* stream) {
                      : ghosts<double>(c, (double*)Q, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "ghost kernels");
   return LES_OK;
+}
+
+int les_residual_reference(les_ctx* c, void* Q, void* R, void* stream) {
+  int r = ready(c);
+  if (r != LES_OK) return r;
+  if (!Q || !R) return fail(c, LES_EINVAL, "Q or R is NULL");
+  if (Q == R) return fail(c, LES_EINVAL, "Q and R must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  if (c->p.precision == LES_FP32_STORAGE) return residual_ref_into<float>(c, (float*)Q, (float*)R, s);
+  return residual_ref_into<double>(c, (double*)Q, (double*)R, s);
 }
 
 int les_residual(les_ctx* c, void* Q, void* R, void* stream) {
@@ -340,11 +399,12 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
   const size_t fb = (size_t)5 * c->g.vs * sizeof(T);
   int r = dalloc(c, &c->stage[0], fb, "stage state");
   if (r == LES_OK) r = dalloc(c, &c->stage[1], fb, "stage state");
-  if (r == LES_OK) r = dalloc(c, &c->R, fb, "residual");
   if (r != LES_OK) return r;
   const bool fp32 = sizeof(T) == sizeof(float);
+  const bool cfl = dt_fixed <= 0.0;
   T* S0 = (T*)c->stage[0];
   T* S1 = (T*)c->stage[1];
+  const T* M = (const T*)c->M;
   hipError_t e = launch_reset(c->maxbits, c->flag, s);
   // FP32 storage: the stage-0 state is an FP32 copy of Q^n
   T* cur = (T*)Qn;
@@ -353,8 +413,9 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
     cur = S1;
   }
   for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
-    e = ghosts<T>(c, cur, s);
-    if (e == hipSuccess && dt_fixed <= 0.0) {
+    // dt of this step: the first step reduces over Q^n here, later steps
+    // take the maximum accumulated by the previous step's last stage
+    if (cfl && n == 0) {
       if (fp32) e = launch_lambda_max<double, float>(Qn, (const float*)c->M, c->g, c->ph64, c->maxbits, s);
       else e = launch_lambda_max<double, double>(Qn, (const double*)c->M, c->g, c->ph64, c->maxbits, s);
     }
@@ -363,22 +424,22 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
                              c->flag, s);
     T* src = cur;
     for (int l = 0; l < 5 && e == hipSuccess; ++l) {
-      if (l > 0) e = ghosts<T>(c, src, s);
-      if (e != hipSuccess) break;
-      e = launch_residual_ref<T>(src, (const T*)c->M, c->g, phys<T>(c), (T*)c->PT, (T*)c->R, s);
+      e = ghosts<T>(c, src, s);
       if (e != hipSuccess) break;
       T* dst;
+      double* q64 = nullptr;
+      int epi = FUSED_EPI_RK;
       if (l < 4) {
         dst = (src == S0) ? S1 : S0;
-        e = launch_rk_update<T, T>(Qn, (const T*)c->R, dst, nullptr, c->g, c->p.rk_alpha[l], c->dt, s);
-      } else if (!fp32) {
-        dst = (T*)Qn;
-        e = launch_rk_update<T, T>(Qn, (const T*)c->R, dst, nullptr, c->g, c->p.rk_alpha[l], c->dt, s);
       } else {
-        // Q^(n+1) in FP64 and its FP32 copy for the next step
-        dst = (src == S0) ? S1 : S0;
-        e = launch_rk_update<T, T>(Qn, (const T*)c->R, dst, Qn, c->g, c->p.rk_alpha[l], c->dt, s);
+        epi = (cfl && n + 1 < nsteps) || fp32 ? FUSED_EPI_RK_LAST : FUSED_EPI_RK;
+        if (fp32) { dst = (src == S0) ? S1 : S0; q64 = Qn; }   // Q^(n+1) in FP64 + FP32 copy
+        else dst = (T*)Qn;
       }
+      const long k = prof_begin(c, s);
+      e = launch_fused<T>(src, M, c->g, phys<T>(c), c->kc, epi, dst, Qn, q64, c->p.rk_alpha[l],
+                          c->dt, c->ph64, c->maxbits, s);
+      prof_end(c, k, s);
       src = dst;
     }
     cur = src;
@@ -400,10 +461,29 @@ int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed, double
   if (!std::isfinite(dt_fixed)) return fail(c, LES_EINVAL, "dt_fixed must be finite");
   if (nsteps == 0) return LES_OK;
   hipStream_t s = (hipStream_t)stream;
-  r = dalloc(c, &c->PT, (size_t)21 * c->g.vs * storage_size(&c->p), "point scratch");
-  if (r != LES_OK) return r;
   if (c->p.precision == LES_FP32_STORAGE) return rk5_steps<float>(c, Qn, nsteps, dt_fixed, dt_out, s);
   return rk5_steps<double>(c, Qn, nsteps, dt_fixed, dt_out, s);
+}
+
+int les_profile(les_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, LES_EINVAL, "ctx is NULL");
+  c->prof = enable != 0;
+  return LES_OK;
+}
+
+int les_profile_read(les_ctx* c, int64_t* launches, double* total_ms) {
+  if (!c) return fail(nullptr, LES_EINVAL, "ctx is NULL");
+  double tot = 0.0;
+  for (size_t k = 0; k < c->ev_used; ++k) {
+    HIP_TRY(c, hipEventSynchronize(c->ev[2 * k + 1]));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)c->ev_used;
+  if (total_ms) *total_ms = tot;
+  c->ev_used = 0;
+  return LES_OK;
 }
 
 int les_query(const les_ctx* c, int64_t dims[3], int64_t* var_stride, size_t* device_bytes) {
@@ -421,6 +501,7 @@ const char* les_last_error(const les_ctx* c) {
 void les_free(les_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   free_all(c);
   delete c;
 }

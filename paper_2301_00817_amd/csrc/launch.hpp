@@ -21,6 +21,15 @@ template <typename T>
 hipError_t launch_residual_ref(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, T* PT,
                                T* R, hipStream_t s);
 
+int fused_chunk(const Grid& g, int num_cu);
+
+template <typename T>
+hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, int kc, int epi,
+                        T* out, const double* Q0, double* Q64, double alpha, const double* dt,
+                        const Phys<double>& ph64, unsigned long long* maxbits, hipStream_t s);
+
+enum { FUSED_EPI_R = 0, FUSED_EPI_RK = 1, FUSED_EPI_RK_LAST = 2 };
+
 template <typename TQ, typename TM>
 hipError_t launch_lambda_max(const TQ* Q, const TM* M, const Grid& g, const Phys<double>& ph,
                              unsigned long long* maxbits, hipStream_t s);

@@ -1,0 +1,400 @@
+// Fused residual / Runge-Kutta stage kernel (section "Spatial
+// Discretization" with the stage update of eq. localdt as an epilogue).
+//
+// Work decomposition (2.5-D): a block of 64 x 8 threads owns a ring-1 tile
+// of (i, j) columns and marches along k over a chunk of planes.  For each
+// plane kk it
+//   (a) writes the state and primitives of the plane (ring-2 tile, two-point
+//       halo for the fourth differences) to LDS,
+//   (b) computes the point quantities G^d, lambda_bar^d, nu^d of every
+//       ring-1 column, with in-plane neighbours from LDS and the kk-1, kk+1
+//       neighbours from the thread's own registers, and publishes the xi and
+//       eta ones in LDS,
+//   (c) forms the in-plane face fluxes of the interior columns from LDS and
+//       the zeta face kk-1/2 from registers (point quantities of plane kk-1
+//       are kept from the previous iteration), which completes R at plane
+//       kk-1.
+// Every point quantity of a ring-1 column is computed once per plane; the
+// in-plane faces are evaluated once from each side.  HBM traffic per
+// interior point and stage: Q (in), the 10 metric arrays, Q^(0) and the
+// output, the halos coming from L2.
+//
+// Epilogues: EPI_R writes R; EPI_RK writes Q^(l) = Q^(0) - alpha dt R
+// (accumulated in FP64, stored in the stage type); EPI_RK_LAST also writes
+// Q^(n+1) in FP64 and reduces max(lambda_xi + lambda_eta + lambda_zeta) of
+// the new state for the next step's dt.
+#include "launch.hpp"
+#include "physics.hpp"
+
+namespace lesjet {
+
+constexpr int FB_X = 64;              // threads along i (ring-1 columns)
+constexpr int FB_Y = 8;               // threads along j
+constexpr int FT_X = FB_X - 2;        // interior outputs along i
+constexpr int FT_Y = FB_Y - 2;        // interior outputs along j
+constexpr int FR_X = FB_X + 2;        // ring-2 tile
+constexpr int FR_Y = FB_Y + 2;
+constexpr int NBORDER = FR_X * FR_Y - FB_X * FB_Y;   // ring-2 points without a thread
+constexpr int NPQ = 8;                // G(5), lambda_bar, nu, V per direction
+
+enum { EPI_R = 0, EPI_RK = 1, EPI_RK_LAST = 2 };
+
+template <typename T>
+__device__ __forceinline__ void load_q(const T* __restrict__ Q, const Grid& g, int i, int j, int k,
+                                       T q[5]) {
+  if (i >= -NG && i < g.nx + NG && j >= -NG && j < g.nr + NG) {
+    const int o = g.at(i, j, k);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) q[c] = Q[(long long)c * g.vs + o];
+  } else {
+    // outside the padded box: a harmless finite state, never used by an output
+    q[0] = T(1); q[1] = T(0); q[2] = T(0); q[3] = T(0); q[4] = T(2.5);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void prim5(const T q[5], const Phys<T>& ph, T p[5]) {
+  const Prim<T> s = primitives(q, ph);
+  p[0] = s.u; p[1] = s.v; p[2] = s.w; p[3] = temperature(s, ph); p[4] = s.p;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_metrics(const T* __restrict__ M, const Grid& g, int i, int j,
+                                             int k, bool ok, T m[10]) {
+  if (ok) {
+    const int o = g.at(i, j, k);
+#pragma unroll
+    for (int c = 0; c < 10; ++c) m[c] = M[(long long)c * g.vs + o];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 10; ++c) m[c] = (c == 0 || c == 4 || c == 8 || c == 9) ? T(1) : T(0);
+  }
+}
+
+template <typename T, int EPI>
+__global__ void __launch_bounds__(FB_X * FB_Y)
+k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, int kc,
+        T* out, const double* Q0, double* Q64, double alpha,
+        const double* __restrict__ dtp, Phys<double> ph64, unsigned long long* __restrict__ maxbits) {
+  __shared__ T sQ[5][FR_Y][FR_X];
+  __shared__ T sP[5][FR_Y][FR_X];
+  __shared__ T sX[NPQ][FB_Y][FB_X];
+  __shared__ T sE[NPQ][FB_Y][FB_X];
+  __shared__ double sRed[FB_X * FB_Y / 64];
+
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * FB_X + tx;
+  const int i0 = blockIdx.x * FT_X, j0 = blockIdx.y * FT_Y;
+  const int k0 = blockIdx.z * kc;
+  const int k1 = min(k0 + kc, g.nth);
+  const int i = i0 - 1 + tx, j = j0 - 1 + ty;
+  const bool col_ok = i >= -1 && i <= g.nx && j >= -1 && j <= g.nr;   // needed ring-1 column
+  const bool interior = tx >= 1 && tx <= FT_X && ty >= 1 && ty <= FT_Y && i < g.nx && j < g.nr;
+
+  // ring-2 border point handled by this thread (if tid < NBORDER)
+  const bool has_b = tid < NBORDER;
+  int brx = 0, bry = 0;
+  if (tid < FR_X) { bry = 0; brx = tid; }
+  else if (tid < 2 * FR_X) { bry = FR_Y - 1; brx = tid - FR_X; }
+  else { const int r = tid - 2 * FR_X; bry = 1 + (r >> 1); brx = (r & 1) ? FR_X - 1 : 0; }
+  const int bi = i0 - 2 + brx, bj = j0 - 2 + bry;
+
+  // physical-boundary faces of this column
+  const bool phys_im = i == 0 && ph.phys_face[0][0];
+  const bool phys_ip = i == g.nx - 1 && ph.phys_face[0][1];
+  const bool phys_jm = j == 0 && ph.phys_face[1][0];
+  const bool phys_jp = j == g.nr - 1 && ph.phys_face[1][1];
+
+  // ---- rolling column state ------------------------------------------------
+  T Wa[5], Wb[5];        // W at kk-2, kk-1
+  T Qc[5], Qd[5], Qe[5]; // Q at kk, kk+1, kk+2 (prefetch)
+  T Pb[5], Pc[5], Pd[5]; // primitives (u, v, w, T, p) at kk-1, kk, kk+1
+  T Bq[5];               // border point: Q at kk (prefetched one plane ahead)
+  T met[10];             // metrics at (i, j, kk)
+  // zeta-face state of plane kk-1 (interior columns)
+  T Gz[5], lbz = 0, nuz = 0, Vz = 0;
+  T Fz[5];               // zeta face flux kk-3/2
+  T rin[5];              // in-plane part of RHS at kk-1
+  T Sprev[9];            // metrics of plane kk-1 (for the last-stage time-step reduction)
+  double lmax = 0.0;
+
+  {
+    T q[5], pp[5];
+    load_q(Qin, g, i, j, k0 - 2, q);
+    prim5(q, ph, pp);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Wa[c] = q[c];
+    Wa[4] += pp[4];
+    load_q(Qin, g, i, j, k0 - 1, q);
+    prim5(q, ph, Pc);           // becomes "kk" at the first iteration (kk = k0 - 1)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Qc[c] = q[c];
+    // primitives at kk-1 = k0-2 for the first iteration
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Pb[c] = pp[c];
+    load_q(Qin, g, i, j, k0, Qd);
+    prim5(Qd, ph, Pd);
+    load_q(Qin, g, i, j, k0 + 1, Qe);
+    if (has_b) load_q(Qin, g, bi, bj, k0 - 1, Bq);
+    load_metrics(M, g, i, j, k0 - 1, col_ok, met);
+  }
+  // Wb (kk-1 = k0-2) is Wa at entry; shift below keeps the window consistent
+#pragma unroll
+  for (int c = 0; c < 5; ++c) { Wb[c] = Wa[c]; Gz[c] = 0; Fz[c] = 0; rin[c] = 0; }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) Sprev[c] = 0;
+
+  for (int kk = k0 - 1; kk <= k1; ++kk) {
+    // (a) plane kk into LDS: own column and the ring-2 border
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      sQ[c][ty + 1][tx + 1] = Qc[c];
+      sP[c][ty + 1][tx + 1] = Pc[c];
+    }
+    if (has_b) {
+      T pb[5];
+      prim5(Bq, ph, pb);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        sQ[c][bry][brx] = Bq[c];
+        sP[c][bry][brx] = pb[c];
+      }
+    }
+    // prefetch for the next plane
+    T Qn2[5], Bn[5], metn[10];
+    const bool more = kk < k1;
+    if (more) {
+      // Q(kk+3) is only consumed if plane kk+2 is iterated (kk+2 <= k1)
+      if (kk + 2 <= k1) load_q(Qin, g, i, j, kk + 3, Qn2);
+      if (has_b) load_q(Qin, g, bi, bj, kk + 1, Bn);
+      load_metrics(M, g, i, j, kk + 1, col_ok, metn);
+    }
+    __syncthreads();
+
+    // (b) point quantities at (i, j, kk)
+    PointIn<T> in;
+    PointOut<T> po;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) in.q[c] = Qc[c];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      in.nb[0][0][f] = sP[f][ty + 1][tx];
+      in.nb[0][1][f] = sP[f][ty + 1][tx + 2];
+      in.nb[1][0][f] = sP[f][ty][tx + 1];
+      in.nb[1][1][f] = sP[f][ty + 2][tx + 1];
+      in.nb[2][0][f] = Pb[f];
+      in.nb[2][1][f] = Pd[f];
+    }
+    in.pn[0][0] = sP[4][ty + 1][tx];
+    in.pn[0][1] = sP[4][ty + 1][tx + 2];
+    in.pn[1][0] = sP[4][ty][tx + 1];
+    in.pn[1][1] = sP[4][ty + 2][tx + 1];
+    in.pn[2][0] = Pb[4];
+    in.pn[2][1] = Pd[4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) in.S[d][c] = met[3 * d + c];
+    in.V = met[9];
+    point_quantities(in, ph, po);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      sX[c][ty][tx] = po.G[0][c];
+      sE[c][ty][tx] = po.G[1][c];
+    }
+    sX[5][ty][tx] = po.lb[0];
+    sX[6][ty][tx] = po.nu[0];
+    sX[7][ty][tx] = in.V;
+    sE[5][ty][tx] = po.lb[1];
+    sE[6][ty][tx] = po.nu[1];
+    sE[7][ty][tx] = in.V;
+    __syncthreads();
+
+    // (c) faces of the interior columns
+    if (interior && kk >= k0) {
+      T Wl[4][5];
+      // in-plane faces (output planes only); W = Q with E replaced by E + p
+      T rhs[5] = {0, 0, 0, 0, 0};
+      if (kk < k1) {
+        // xi: points tx-1 .. tx+3 in ring-2 coordinates are i-2 .. i+2
+        T W5[5][5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) W5[m][c] = sQ[c][ty + 1][tx - 1 + m];
+          W5[m][4] = sQ[4][ty + 1][tx - 1 + m] + sP[4][ty + 1][tx - 1 + m];
+        }
+        T GL[5], GC[5], GR[5], Fm[5], Fp[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          GL[c] = sX[c][ty][tx - 1];
+          GC[c] = sX[c][ty][tx];
+          GR[c] = sX[c][ty][tx + 1];
+        }
+        face_flux(GL, GC, sX[5][ty][tx - 1], sX[5][ty][tx], sX[6][ty][tx - 1], sX[6][ty][tx],
+                  sX[7][ty][tx - 1], sX[7][ty][tx], W5[0], W5[1], W5[2], W5[3], phys_im, ph, Fm);
+        face_flux(GC, GR, sX[5][ty][tx], sX[5][ty][tx + 1], sX[6][ty][tx], sX[6][ty][tx + 1],
+                  sX[7][ty][tx], sX[7][ty][tx + 1], W5[1], W5[2], W5[3], W5[4], phys_ip, ph, Fp);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) rhs[c] = Fp[c] - Fm[c];
+      }
+      if (kk < k1) {
+        T W5[5][5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) W5[m][c] = sQ[c][ty - 1 + m][tx + 1];
+          W5[m][4] = sQ[4][ty - 1 + m][tx + 1] + sP[4][ty - 1 + m][tx + 1];
+        }
+        T GL[5], GC[5], GR[5], Fm[5], Fp[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          GL[c] = sE[c][ty - 1][tx];
+          GC[c] = sE[c][ty][tx];
+          GR[c] = sE[c][ty + 1][tx];
+        }
+        face_flux(GL, GC, sE[5][ty - 1][tx], sE[5][ty][tx], sE[6][ty - 1][tx], sE[6][ty][tx],
+                  sE[7][ty - 1][tx], sE[7][ty][tx], W5[0], W5[1], W5[2], W5[3], phys_jm, ph, Fm);
+        face_flux(GC, GR, sE[5][ty][tx], sE[5][ty + 1][tx], sE[6][ty][tx], sE[6][ty + 1][tx],
+                  sE[7][ty][tx], sE[7][ty + 1][tx], W5[1], W5[2], W5[3], W5[4], phys_jp, ph, Fp);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) rhs[c] += Fp[c] - Fm[c];
+      }
+      // zeta face kk-1/2: L = kk-1 (registers), R = kk
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Wl[0][c] = Wa[c]; Wl[1][c] = Wb[c]; Wl[2][c] = Qc[c]; Wl[3][c] = Qd[c];
+      }
+      Wl[0][4] = Wa[4]; Wl[1][4] = Wb[4]; Wl[2][4] = Qc[4] + Pc[4]; Wl[3][4] = Qd[4] + Pd[4];
+      T Fk[5];
+      face_flux(Gz, po.G[2], lbz, po.lb[2], nuz, po.nu[2], Vz, in.V, Wl[0], Wl[1], Wl[2], Wl[3],
+                false, ph, Fk);
+      if (kk - 1 >= k0) {
+        // R at (i, j, kk-1) is complete
+        const int o = g.at(i, j, kk - 1);
+        const T iV = T(1) / Vz;
+        T R[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) R[c] = (rin[c] + Fk[c] - Fz[c]) * iV;
+        if (EPI == EPI_R) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) out[(long long)c * g.vs + o] = R[c];
+        } else {
+          const double ad = alpha * (*dtp);
+          double qn[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            const long long oc = (long long)c * g.vs + o;
+            qn[c] = Q0[oc] - ad * (double)R[c];
+            out[oc] = (T)qn[c];
+            if (EPI == EPI_RK_LAST && Q64) Q64[oc] = qn[c];
+          }
+          if (EPI == EPI_RK_LAST) {
+            double S[3][3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) S[d][c] = (double)Sprev[3 * d + c];
+            const double x = lambda_sum(qn, S, (double)Vz, ph64);
+            if (x != x || x > lmax) lmax = x;
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        Fz[c] = Fk[c];
+        rin[c] = rhs[c];
+      }
+    }
+    // keep the zeta-direction point quantities of plane kk
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Gz[c] = po.G[2][c];
+    lbz = po.lb[2];
+    nuz = po.nu[2];
+    Vz = in.V;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Sprev[c] = met[c];
+    // roll the column window by one plane
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      Wa[c] = Wb[c];
+      Wb[c] = Qc[c];
+      Pb[c] = Pc[c];
+    }
+    Wb[4] = Qc[4] + Pc[4];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      Qc[c] = Qd[c];
+      Pc[c] = Pd[c];
+      Qd[c] = Qe[c];
+    }
+    if (more) {
+      prim5(Qd, ph, Pd);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) { Qe[c] = Qn2[c]; Bq[c] = Bn[c]; }
+#pragma unroll
+      for (int c = 0; c < 10; ++c) met[c] = metn[c];
+    }
+    __syncthreads();
+  }
+
+  if (EPI == EPI_RK_LAST) {
+    // block max of the lambda sums, then one integer atomic per block
+    double v = lmax;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v, off, 64);
+      if (o != o || o > v) v = o;
+    }
+    if ((tid & 63) == 0) sRed[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double b = sRed[0];
+      for (int w = 1; w < FB_X * FB_Y / 64; ++w)
+        if (sRed[w] != sRed[w] || sRed[w] > b) b = sRed[w];
+      atomicMax(maxbits, (unsigned long long)__double_as_longlong(b));
+    }
+  }
+}
+
+int fused_chunk(const Grid& g, int num_cu) {
+  const long long tiles = (long long)((g.nx + FT_X - 1) / FT_X) * ((g.nr + FT_Y - 1) / FT_Y);
+  // pick the chunk length that minimises (rounds of resident blocks) x (planes per block)
+  int best = g.nth;
+  double best_cost = 1e300;
+  for (int kc = 4; kc <= 64; kc *= 2) {
+    const long long nb = tiles * ((g.nth + kc - 1) / kc);
+    const long long rounds = (nb + num_cu - 1) / num_cu;
+    const double cost = (double)rounds * (kc + 2);
+    if (cost < best_cost) { best_cost = cost; best = kc; }
+  }
+  return best;
+}
+
+template <typename T>
+hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, int kc, int epi,
+                        T* out, const double* Q0, double* Q64, double alpha, const double* dt,
+                        const Phys<double>& ph64, unsigned long long* maxbits, hipStream_t s) {
+  const dim3 grid((g.nx + FT_X - 1) / FT_X, (g.nr + FT_Y - 1) / FT_Y, (g.nth + kc - 1) / kc);
+  const dim3 block(FB_X, FB_Y, 1);
+  if (epi == EPI_R)
+    hipLaunchKernelGGL((k_fused<T, EPI_R>), grid, block, 0, s, Q, M, g, ph, kc, out, Q0, Q64,
+                       alpha, dt, ph64, maxbits);
+  else if (epi == EPI_RK)
+    hipLaunchKernelGGL((k_fused<T, EPI_RK>), grid, block, 0, s, Q, M, g, ph, kc, out, Q0, Q64,
+                       alpha, dt, ph64, maxbits);
+  else
+    hipLaunchKernelGGL((k_fused<T, EPI_RK_LAST>), grid, block, 0, s, Q, M, g, ph, kc, out, Q0,
+                       Q64, alpha, dt, ph64, maxbits);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fused<double>(const double*, const double*, const Grid&,
+                                         const Phys<double>&, int, int, double*, const double*,
+                                         double*, double, const double*, const Phys<double>&,
+                                         unsigned long long*, hipStream_t);
+template hipError_t launch_fused<float>(const float*, const float*, const Grid&, const Phys<float>&,
+                                        int, int, float*, const double*, double*, double,
+                                        const double*, const Phys<double>&, unsigned long long*,
+                                        hipStream_t);
+
+}  // namespace lesjet

@@ -84,6 +84,14 @@ class Solver:
         B.les_residual(self.ctx, Qp.data_ptr(), R.data_ptr(), _stream(self.device))
         return R
 
+    def residual_reference(self, Qp, R=None):
+        """R(Q) by the two-pass reference kernels (validation)."""
+        assert Qp.dtype == self.dtype and tuple(Qp.shape) == (5,) + self.dims and Qp.is_contiguous()
+        if R is None:
+            R = self.field(5, fill=float("nan"))
+        B.les_residual_reference(self.ctx, Qp.data_ptr(), R.data_ptr(), _stream(self.device))
+        return R
+
     def rk5_step(self, Qn, nsteps=1, dt=0.0, dt_out=None):
         """Advance the padded FP64 state Qn in place; returns the per-step dt
         (device tensor of nsteps doubles)."""
@@ -93,6 +101,14 @@ class Solver:
         B.les_rk5_step(self.ctx, Qn.data_ptr(), int(nsteps), float(dt), dt_out.data_ptr(),
                        _stream(self.device))
         return dt_out
+
+    def profile(self, enable=True):
+        B.les_profile(self.ctx, enable)
+
+    def profile_read(self):
+        """(launches, total ms) of the residual stage kernel since the last
+        read, timed with HIP events on the launch stream."""
+        return B.les_profile_read(self.ctx)
 
     def query(self):
         return B.les_query(self.ctx)

@@ -34,8 +34,24 @@ template <> __host__ __device__ __forceinline__ float tcbrt<float>(float x) { re
 template <typename T> __host__ __device__ __forceinline__ T tpow(T x, T y);
 template <> __host__ __device__ __forceinline__ double tpow<double>(double x, double y) { return pow(x, y); }
 template <> __host__ __device__ __forceinline__ float tpow<float>(float x, float y) { return powf(x, y); }
-template <typename T> __host__ __device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
-template <typename T> __host__ __device__ __forceinline__ T tmax(T a, T b) { return a >= b ? a : b; }
+template <typename T> __host__ __device__ __forceinline__ T tabs(T x);
+template <> __host__ __device__ __forceinline__ double tabs<double>(double x) { return fabs(x); }
+template <> __host__ __device__ __forceinline__ float tabs<float>(float x) { return fabsf(x); }
+template <typename T> __host__ __device__ __forceinline__ T tmax(T a, T b);
+template <> __host__ __device__ __forceinline__ double tmax<double>(double a, double b) { return fmax(a, b); }
+template <> __host__ __device__ __forceinline__ float tmax<float>(float a, float b) { return fmaxf(a, b); }
+
+// Reciprocal: correctly rounded in FP64; the hardware approximation (1 ulp)
+// in FP32, which serves only the FP32-storage form.
+template <typename T> __host__ __device__ __forceinline__ T trcp(T x);
+template <> __host__ __device__ __forceinline__ double trcp<double>(double x) { return 1.0 / x; }
+template <> __host__ __device__ __forceinline__ float trcp<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
 
 // Primitive variables from Q = (rho, rho u, rho v, rho w, E); System-I energy
 // E = p/(gamma-1) + rho |u|^2/2.
@@ -46,7 +62,7 @@ template <typename T>
 __host__ __device__ __forceinline__ Prim<T> primitives(const T q[5], const Phys<T>& ph) {
   Prim<T> s;
   s.rho = q[0];
-  const T ir = T(1) / q[0];
+  const T ir = trcp(q[0]);
   s.u = q[1] * ir;
   s.v = q[2] * ir;
   s.w = q[3] * ir;
@@ -57,19 +73,45 @@ __host__ __device__ __forceinline__ Prim<T> primitives(const T q[5], const Phys<
 // Temperature in jet units: p = rho T / gamma.
 template <typename T>
 __host__ __device__ __forceinline__ T temperature(const Prim<T>& s, const Phys<T>& ph) {
-  return ph.gamma * s.p / s.rho;
+  return ph.gamma * s.p * trcp(s.rho);
 }
 
-// Data a point needs: its state, (u, v, w, T) and p of its six neighbours,
-// its metrics.
+// (u, v, w, T, p) of a state, the form the point computation consumes.
+template <typename T>
+__host__ __device__ __forceinline__ void prim5(const T q[5], const Phys<T>& ph, T pr[5]) {
+  const T ir = trcp(q[0]);
+  pr[0] = q[1] * ir;
+  pr[1] = q[2] * ir;
+  pr[2] = q[3] * ir;
+  pr[4] = ph.gm1 * (q[4] - T(0.5) * q[0] * (pr[0] * pr[0] + pr[1] * pr[1] + pr[2] * pr[2]));
+  pr[3] = ph.gamma * pr[4] * ir;
+}
+
+// Data a point needs: its state and primitives, the central differences of
+// (u, v, w, T) and the pressure sensors along the three index directions
+// (formed by the caller from the six neighbours, see `neighbour_terms`), its
+// metrics.
 template <typename T>
 struct PointIn {
   T q[5];
-  T nb[3][2][4];     // [direction][0: -1, 1: +1][u, v, w, T]
-  T pn[3][2];        // pressure of the neighbours
+  T pr[5];           // (u, v, w, T, p) of the point, from prim5
+  T dl[3][4];        // (phi_{+1} - phi_{-1}) / 2 along d, phi = (u, v, w, T)
+  T nu[3];           // pressure sensor along d
   T S[3][3];         // S[d] = J^-1 grad(xi_d)
   T V;               // J^-1
 };
+
+// Central differences and pressure sensor along one direction from the
+// (u, v, w, T, p) of the -1 and +1 neighbours; p is the point's pressure.
+template <typename T>
+__host__ __device__ __forceinline__ void neighbour_terms(const T m[5], const T pl[5], T p, T dl[4],
+                                                         T& nu) {
+#pragma unroll
+  for (int f = 0; f < 4; ++f) dl[f] = T(0.5) * (pl[f] - m[f]);
+  const T num = pl[4] - T(2) * p + m[4];
+  const T den = pl[4] + T(2) * p + m[4];
+  nu = tabs(num) * trcp(den);
+}
 
 template <typename T>
 struct PointOut {
@@ -81,10 +123,11 @@ struct PointOut {
 template <typename T>
 __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phys<T>& ph,
                                                  PointOut<T>& out) {
-  const Prim<T> s = primitives(in.q, ph);
-  const T Tt = temperature(s, ph);
+  Prim<T> s;
+  s.rho = in.q[0]; s.u = in.pr[0]; s.v = in.pr[1]; s.w = in.pr[2]; s.p = in.pr[4];
+  const T Tt = in.pr[3];
   const T a = tsqrt(Tt);                       // a^2 = gamma p / rho = T
-  const T iV = T(1) / in.V;
+  const T iV = trcp(in.V);
   const T aiV = tabs(iV);
 
   T Uc[3];
@@ -101,16 +144,14 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
   }
 
   if (ph.viscous) {
-    // central differences and the chain rule
-    T dl[3][4];
-    for (int d = 0; d < 3; ++d)
-      for (int f = 0; f < 4; ++f) dl[d][f] = T(0.5) * (in.nb[d][1][f] - in.nb[d][0][f]);
+    // chain rule on the central differences
+    const T (&dl)[3][4] = in.dl;
     T g[4][3];   // g[f][m] = d phi_f / d x_m, phi = (u, v, w, T)
     for (int f = 0; f < 4; ++f)
       for (int m = 0; m < 3; ++m)
         g[f][m] = (in.S[0][m] * dl[0][f] + in.S[1][m] * dl[1][f] + in.S[2][m] * dl[2][f]) * iV;
 
-    const T mu = Tt * a * ph.suth1 / (Tt + ph.suth);      // Sutherland
+    const T mu = Tt * a * ph.suth1 * trcp(Tt + ph.suth);      // Sutherland
     T mut = T(0);
     if (ph.sgs) {
       T s2 = T(0);
@@ -154,12 +195,7 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
   out.lb[1] = lam[1] + s01 + s12;
   out.lb[2] = lam[2] + s02 + s12;
 
-  // pressure sensors
-  for (int d = 0; d < 3; ++d) {
-    const T num = in.pn[d][1] - T(2) * s.p + in.pn[d][0];
-    const T den = in.pn[d][1] + T(2) * s.p + in.pn[d][0];
-    out.nu[d] = tabs(num) / den;
-  }
+  for (int d = 0; d < 3; ++d) out.nu[d] = in.nu[d];
 }
 
 // Dissipation vector W = (rho, rho u, rho v, rho w, E + p).

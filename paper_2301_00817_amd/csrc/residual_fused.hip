@@ -53,12 +53,6 @@ __device__ __forceinline__ void load_q(const T* __restrict__ Q, const Grid& g, i
 }
 
 template <typename T>
-__device__ __forceinline__ void prim5(const T q[5], const Phys<T>& ph, T p[5]) {
-  const Prim<T> s = primitives(q, ph);
-  p[0] = s.u; p[1] = s.v; p[2] = s.w; p[3] = temperature(s, ph); p[4] = s.p;
-}
-
-template <typename T>
 __device__ __forceinline__ void load_metrics(const T* __restrict__ M, const Grid& g, int i, int j,
                                              int k, bool ok, T m[10]) {
   if (ok) {
@@ -106,68 +100,58 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
   const bool phys_jp = j == g.nr - 1 && ph.phys_face[1][1];
 
   // ---- rolling column state ------------------------------------------------
-  T Wa[5], Wb[5];        // W at kk-2, kk-1
-  T Qc[5], Qd[5], Qe[5]; // Q at kk, kk+1, kk+2 (prefetch)
-  T Pb[5], Pc[5], Pd[5]; // primitives (u, v, w, T, p) at kk-1, kk, kk+1
-  T Bq[5];               // border point: Q at kk (prefetched one plane ahead)
-  T met[10];             // metrics at (i, j, kk)
+  // The state and primitives of the current plane kk live in LDS once phase
+  // (a) has written them; registers carry only what the march needs next.
+  T Wa[5], Wb[5];        // W at kk-2, kk-1 (zeta fourth difference)
+  T Qd[5], Pd[5];        // Q and (u, v, w, T, p) at kk+1
+  T Pb[5];               // (u, v, w, T, p) at kk-1
+  T Qn[5];               // Q at kk+2, in flight
+  T met[10], metn[10];   // metrics at (i, j, kk) and the prefetch for kk+1
   // zeta-face state of plane kk-1 (interior columns)
   T Gz[5], lbz = 0, nuz = 0, Vz = 0;
-  T Fz[5];               // zeta face flux kk-3/2
-  T rin[5];              // in-plane part of RHS at kk-1
-  T Sprev[9];            // metrics of plane kk-1 (for the last-stage time-step reduction)
+  T acc[5];              // RHS at kk-1 without its zeta face kk-1/2:
+                         // in-plane faces minus the zeta face kk-3/2
   double lmax = 0.0;
 
   {
-    T q[5], pp[5];
+    T q[5], pc[5];
     load_q(Qin, g, i, j, k0 - 2, q);
-    prim5(q, ph, pp);
+    prim5(q, ph, Pb);                    // primitives at kk-1 = k0-2
 #pragma unroll
     for (int c = 0; c < 5; ++c) Wa[c] = q[c];
-    Wa[4] += pp[4];
-    load_q(Qin, g, i, j, k0 - 1, q);
-    prim5(q, ph, Pc);           // becomes "kk" at the first iteration (kk = k0 - 1)
-#pragma unroll
-    for (int c = 0; c < 5; ++c) Qc[c] = q[c];
-    // primitives at kk-1 = k0-2 for the first iteration
-#pragma unroll
-    for (int c = 0; c < 5; ++c) Pb[c] = pp[c];
-    load_q(Qin, g, i, j, k0, Qd);
-    prim5(Qd, ph, Pd);
-    load_q(Qin, g, i, j, k0 + 1, Qe);
-    if (has_b) load_q(Qin, g, bi, bj, k0 - 1, Bq);
-    load_metrics(M, g, i, j, k0 - 1, col_ok, met);
-  }
-  // Wb (kk-1 = k0-2) is Wa at entry; shift below keeps the window consistent
-#pragma unroll
-  for (int c = 0; c < 5; ++c) { Wb[c] = Wa[c]; Gz[c] = 0; Fz[c] = 0; rin[c] = 0; }
-#pragma unroll
-  for (int c = 0; c < 9; ++c) Sprev[c] = 0;
-
-  for (int kk = k0 - 1; kk <= k1; ++kk) {
-    // (a) plane kk into LDS: own column and the ring-2 border
+    Wa[4] += Pb[4];
+    load_q(Qin, g, i, j, k0 - 1, q);     // plane kk = k0-1 of the own column
+    prim5(q, ph, pc);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      sQ[c][ty + 1][tx + 1] = Qc[c];
-      sP[c][ty + 1][tx + 1] = Pc[c];
+      sQ[c][ty + 1][tx + 1] = q[c];
+      sP[c][ty + 1][tx + 1] = pc[c];
     }
+    load_q(Qin, g, i, j, k0, Qd);
+    prim5(Qd, ph, Pd);
+    load_metrics(M, g, i, j, k0 - 1, col_ok, met);
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) { Wb[c] = Wa[c]; Gz[c] = 0; acc[c] = 0; }
+
+  for (int kk = k0 - 1; kk <= k1; ++kk) {
+    const bool more = kk < k1;
+    // issue the loads of the next planes first
+    if (more) {
+      if (kk + 2 <= k1 + 1) load_q(Qin, g, i, j, kk + 2, Qn);
+      load_metrics(M, g, i, j, kk + 1, col_ok, metn);
+    }
+    // (a) plane kk into LDS: the ring-2 border (the own column was written at
+    // the end of the previous iteration)
     if (has_b) {
-      T pb[5];
-      prim5(Bq, ph, pb);
+      T bq[5], bp[5];
+      load_q(Qin, g, bi, bj, kk, bq);
+      prim5(bq, ph, bp);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        sQ[c][bry][brx] = Bq[c];
-        sP[c][bry][brx] = pb[c];
+        sQ[c][bry][brx] = bq[c];
+        sP[c][bry][brx] = bp[c];
       }
-    }
-    // prefetch for the next plane
-    T Qn2[5], Bn[5], metn[10];
-    const bool more = kk < k1;
-    if (more) {
-      // Q(kk+3) is only consumed if plane kk+2 is iterated (kk+2 <= k1)
-      if (kk + 2 <= k1) load_q(Qin, g, i, j, kk + 3, Qn2);
-      if (has_b) load_q(Qin, g, bi, bj, kk + 1, Bn);
-      load_metrics(M, g, i, j, kk + 1, col_ok, metn);
     }
     __syncthreads();
 
@@ -175,22 +159,20 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     PointIn<T> in;
     PointOut<T> po;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) in.q[c] = Qc[c];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      in.nb[0][0][f] = sP[f][ty + 1][tx];
-      in.nb[0][1][f] = sP[f][ty + 1][tx + 2];
-      in.nb[1][0][f] = sP[f][ty][tx + 1];
-      in.nb[1][1][f] = sP[f][ty + 2][tx + 1];
-      in.nb[2][0][f] = Pb[f];
-      in.nb[2][1][f] = Pd[f];
+    for (int c = 0; c < 5; ++c) {
+      in.q[c] = sQ[c][ty + 1][tx + 1];
+      in.pr[c] = sP[c][ty + 1][tx + 1];
     }
-    in.pn[0][0] = sP[4][ty + 1][tx];
-    in.pn[0][1] = sP[4][ty + 1][tx + 2];
-    in.pn[1][0] = sP[4][ty][tx + 1];
-    in.pn[1][1] = sP[4][ty + 2][tx + 1];
-    in.pn[2][0] = Pb[4];
-    in.pn[2][1] = Pd[4];
+    {
+      T m[5], pl[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) { m[f] = sP[f][ty + 1][tx]; pl[f] = sP[f][ty + 1][tx + 2]; }
+      neighbour_terms(m, pl, in.pr[4], in.dl[0], in.nu[0]);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) { m[f] = sP[f][ty][tx + 1]; pl[f] = sP[f][ty + 2][tx + 1]; }
+      neighbour_terms(m, pl, in.pr[4], in.dl[1], in.nu[1]);
+      neighbour_terms(Pb, Pd, in.pr[4], in.dl[2], in.nu[2]);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -212,11 +194,9 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
 
     // (c) faces of the interior columns
     if (interior && kk >= k0) {
-      T Wl[4][5];
       // in-plane faces (output planes only); W = Q with E replaced by E + p
       T rhs[5] = {0, 0, 0, 0, 0};
       if (kk < k1) {
-        // xi: points tx-1 .. tx+3 in ring-2 coordinates are i-2 .. i+2
         T W5[5][5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
@@ -237,16 +217,12 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
                   sX[7][ty][tx], sX[7][ty][tx + 1], W5[1], W5[2], W5[3], W5[4], phys_ip, ph, Fp);
 #pragma unroll
         for (int c = 0; c < 5; ++c) rhs[c] = Fp[c] - Fm[c];
-      }
-      if (kk < k1) {
-        T W5[5][5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) W5[m][c] = sQ[c][ty - 1 + m][tx + 1];
           W5[m][4] = sQ[4][ty - 1 + m][tx + 1] + sP[4][ty - 1 + m][tx + 1];
         }
-        T GL[5], GC[5], GR[5], Fm[5], Fp[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
           GL[c] = sE[c][ty - 1][tx];
@@ -261,21 +237,19 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
         for (int c = 0; c < 5; ++c) rhs[c] += Fp[c] - Fm[c];
       }
       // zeta face kk-1/2: L = kk-1 (registers), R = kk
+      T Wc[5], Wd[5], Fk[5];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        Wl[0][c] = Wa[c]; Wl[1][c] = Wb[c]; Wl[2][c] = Qc[c]; Wl[3][c] = Qd[c];
-      }
-      Wl[0][4] = Wa[4]; Wl[1][4] = Wb[4]; Wl[2][4] = Qc[4] + Pc[4]; Wl[3][4] = Qd[4] + Pd[4];
-      T Fk[5];
-      face_flux(Gz, po.G[2], lbz, po.lb[2], nuz, po.nu[2], Vz, in.V, Wl[0], Wl[1], Wl[2], Wl[3],
-                false, ph, Fk);
+      for (int c = 0; c < 5; ++c) { Wc[c] = in.q[c]; Wd[c] = Qd[c]; }
+      Wc[4] += in.pr[4];
+      Wd[4] += Pd[4];
+      face_flux(Gz, po.G[2], lbz, po.lb[2], nuz, po.nu[2], Vz, in.V, Wa, Wb, Wc, Wd, false, ph, Fk);
       if (kk - 1 >= k0) {
         // R at (i, j, kk-1) is complete
         const int o = g.at(i, j, kk - 1);
-        const T iV = T(1) / Vz;
+        const T iV = trcp(Vz);
         T R[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) R[c] = (rin[c] + Fk[c] - Fz[c]) * iV;
+        for (int c = 0; c < 5; ++c) R[c] = (acc[c] + Fk[c]) * iV;
         if (EPI == EPI_R) {
 #pragma unroll
           for (int c = 0; c < 5; ++c) out[(long long)c * g.vs + o] = R[c];
@@ -290,52 +264,44 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
             if (EPI == EPI_RK_LAST && Q64) Q64[oc] = qn[c];
           }
           if (EPI == EPI_RK_LAST) {
-            double S[3][3];
+            double S[3][3];   // metrics of the output point (cached in L2)
 #pragma unroll
             for (int d = 0; d < 3; ++d)
 #pragma unroll
-              for (int c = 0; c < 3; ++c) S[d][c] = (double)Sprev[3 * d + c];
+              for (int c = 0; c < 3; ++c) S[d][c] = (double)M[(long long)(3 * d + c) * g.vs + o];
             const double x = lambda_sum(qn, S, (double)Vz, ph64);
             if (x != x || x > lmax) lmax = x;
           }
         }
       }
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        Fz[c] = Fk[c];
-        rin[c] = rhs[c];
-      }
+      for (int c = 0; c < 5; ++c) acc[c] = rhs[c] - Fk[c];
     }
-    // keep the zeta-direction point quantities of plane kk
+    // keep the zeta-direction point quantities of plane kk, roll the window
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Gz[c] = po.G[2][c];
+    for (int c = 0; c < 5; ++c) {
+      Gz[c] = po.G[2][c];
+      Wa[c] = Wb[c];
+      Wb[c] = in.q[c];
+      Pb[c] = in.pr[c];
+    }
+    Wb[4] += in.pr[4];
     lbz = po.lb[2];
     nuz = po.nu[2];
     Vz = in.V;
-#pragma unroll
-    for (int c = 0; c < 9; ++c) Sprev[c] = met[c];
-    // roll the column window by one plane
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      Wa[c] = Wb[c];
-      Wb[c] = Qc[c];
-      Pb[c] = Pc[c];
-    }
-    Wb[4] = Qc[4] + Pc[4];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      Qc[c] = Qd[c];
-      Pc[c] = Pd[c];
-      Qd[c] = Qe[c];
-    }
+    __syncthreads();
     if (more) {
-      prim5(Qd, ph, Pd);
+      // plane kk+1 of the own column goes straight to LDS
 #pragma unroll
-      for (int c = 0; c < 5; ++c) { Qe[c] = Qn2[c]; Bq[c] = Bn[c]; }
+      for (int c = 0; c < 5; ++c) {
+        sQ[c][ty + 1][tx + 1] = Qd[c];
+        sP[c][ty + 1][tx + 1] = Pd[c];
+        Qd[c] = Qn[c];
+      }
+      prim5(Qd, ph, Pd);
 #pragma unroll
       for (int c = 0; c < 10; ++c) met[c] = metn[c];
     }
-    __syncthreads();
   }
 
   if (EPI == EPI_RK_LAST) {

@@ -11,14 +11,11 @@
 namespace lesjet {
 
 template <typename T>
-__device__ __forceinline__ void uvwTp(const T* Q, int vs, int o, const Phys<T>& ph, T out[4],
-                                      T& p) {
+__device__ __forceinline__ void uvwTp(const T* Q, int vs, int o, const Phys<T>& ph, T out[5]) {
   T q[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) q[c] = Q[(long long)c * vs + o];
-  const Prim<T> s = primitives(q, ph);
-  out[0] = s.u; out[1] = s.v; out[2] = s.w; out[3] = temperature(s, ph);
-  p = s.p;
+  prim5(q, ph, out);
 }
 
 template <typename T>
@@ -36,10 +33,13 @@ __global__ void k_point_pass(const T* __restrict__ Q, const T* __restrict__ M, G
   PointIn<T> in;
 #pragma unroll
   for (int c = 0; c < 5; ++c) in.q[c] = Q[(long long)c * g.vs + o];
+  prim5(in.q, ph, in.pr);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    uvwTp(Q, g.vs, o - step[d], ph, in.nb[d][0], in.pn[d][0]);
-    uvwTp(Q, g.vs, o + step[d], ph, in.nb[d][1], in.pn[d][1]);
+    T m[5], pl[5];
+    uvwTp(Q, g.vs, o - step[d], ph, m);
+    uvwTp(Q, g.vs, o + step[d], ph, pl);
+    neighbour_terms(m, pl, in.pr[4], in.dl[d], in.nu[d]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) in.S[d][c] = M[(long long)(3 * d + c) * g.vs + o];
   }
@@ -94,7 +94,7 @@ __global__ void k_face_pass(const T* __restrict__ Q, const T* __restrict__ M, Gr
               ph, Fp);
     for (int c = 0; c < 5; ++c) rhs[c] += Fp[c] - Fm[c];
   }
-  const T iV = T(1) / M[9LL * g.vs + o];
+  const T iV = trcp(M[9LL * g.vs + o]);
   for (int c = 0; c < 5; ++c) R[(long long)c * g.vs + o] = rhs[c] * iV;
 }
 

@@ -127,8 +127,18 @@ def copy_probe(gib, dev, reps=5):
     e1.record(st)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    # a plain elementwise streaming kernel (dword loads/stores, like the
+    # solver's kernels): reads a, writes b
+    e0.record(st)
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms2 = e0.elapsed_time(e1) / reps
     print(json.dumps({"copy_probe": {"bytes_read": n * 8, "bytes_written": n * 8,
-                                     "ms": ms, "GBps": 2 * n * 8 / ms / 1e6}}), flush=True)
+                                     "copy_ms": ms, "copy_GBps": 2 * n * 8 / ms / 1e6,
+                                     "elementwise_ms": ms2,
+                                     "elementwise_GBps": 2 * n * 8 / ms2 / 1e6}}), flush=True)
 
 
 def rocprof_summary(csv_dir, out_path, command, kernel=DOMINANT_KERNEL):
@@ -146,6 +156,43 @@ def rocprof_summary(csv_dir, out_path, command, kernel=DOMINANT_KERNEL):
     return out_path
 
 
+def _counter_rows(csv_dir):
+    import csv
+    f = [x for x in os.listdir(csv_dir) if x.endswith("counter_collection.csv")][0]
+    return list(csv.DictReader(open(os.path.join(csv_dir, f))))
+
+
+def _median_counter(rows, kernel_prefix, counter):
+    vals = sorted(float(r["Counter_Value"]) for r in rows
+                  if r["Kernel_Name"].startswith(kernel_prefix) and r["Counter_Name"] == counter)
+    return vals[len(vals) // 2] if vals else None, len(vals)
+
+
+def traffic_record(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, known_bytes):
+    """Stage-kernel HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by the ratio known / counted bytes of a plain
+    elementwise streaming kernel; written into profiles/traffic.json."""
+    f, nf = _median_counter(_counter_rows(fetch_dir), DOMINANT_KERNEL, "FETCH_SIZE")
+    w, nw = _median_counter(_counter_rows(write_dir), DOMINANT_KERNEL, "WRITE_SIZE")
+    cf, _ = _median_counter(_counter_rows(cfetch_dir), "vectorized_elementwise", "FETCH_SIZE")
+    cw, _ = _median_counter(_counter_rows(cwrite_dir), "vectorized_elementwise", "WRITE_SIZE")
+    kf = known_bytes / (cf * 1024.0)
+    kw = known_bytes / (cw * 1024.0)
+    rec = {"fetch_kib": f, "write_kib": w, "dispatches": [nf, nw],
+           "calib_fetch_factor": kf, "calib_write_factor": kw,
+           "bytes_per_launch": f * 1024.0 * kf + w * 1024.0 * kw,
+           "source_sha": source_hash()}
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        t = {}
+    t.setdefault(DOMINANT_KERNEL, {})[workload] = rec
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1, sort_keys=True)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,7 +205,15 @@ def main():
                     help="only time a device copy of this many GiB (counter calibration)")
     ap.add_argument("--rocprof-summary", nargs=3, metavar=("CSV_DIR", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 kernel-stats CSV and exit")
+    ap.add_argument("--traffic-from", nargs=6,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR", "WORKLOAD",
+                             "CAL_BYTES"),
+                    help="record stage-kernel HBM traffic from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        a = args.traffic_from
+        print(json.dumps(traffic_record(a[0], a[1], a[2], a[3], a[4], float(a[5]))))
+        return
     if args.rocprof_summary:
         print(rocprof_summary(*args.rocprof_summary))
         return
@@ -176,6 +231,8 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe, dev)
         return
+    from cases import problems
+    kind = problems.CONFIGS[args.config]["kind"]
     prm, xyz, Q, inflow = make_workload(args.config, dev)
     s = Solver(prm, xyz, inflow, precision=args.precision, device=dev)
     del xyz
@@ -227,7 +284,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32-storage/f64-accumulate",
         "data": "synthetic",
         "config": {"workload": f"jet mesh {nx}x{nr}x{nth} ({npts} points), {args.precision}, "
-                               f"CFL {prm['cfl']}, RK5 steps" if "jet" in args.config else
+                               f"CFL {prm['cfl']}, RK5 steps" if kind == "jet" else
                                f"periodic box {nx}^3, {args.precision}, CFL {prm['cfl']}",
                    "points": npts, "precision": args.precision,
                    "dt_last": float(dts[-1])},

@@ -9,7 +9,9 @@ raises immediately — there is no fallback implementation.
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblesjet.so")
+# LESJET_LIB selects another build of the same library (A/B measurements)
+LIB_PATH = os.environ.get("LESJET_LIB") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "_lib", "liblesjet.so")
 
 LES_OK, LES_EINVAL, LES_ENOMEM, LES_EHIP, LES_ENONFINITE, LES_ESTATE, LES_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6

@@ -251,7 +251,8 @@ int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, void* s
   if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipGetDevice"); }
   e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipDeviceGetAttribute"); }
-  c->kc = fused_chunk(c->g, c->num_cu);
+  c->kc = p->precision == LES_FP32_STORAGE ? fused_chunk<float>(c->g, c->num_cu)
+                                          : fused_chunk<double>(c->g, c->num_cu);
   if (const char* kc = std::getenv("LESJET_KCHUNK")) {   // tuning / test override
     const int v = std::atoi(kc);
     if (v >= 1) c->kc = v;

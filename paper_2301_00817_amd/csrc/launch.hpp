@@ -21,6 +21,7 @@ template <typename T>
 hipError_t launch_residual_ref(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, T* PT,
                                T* R, hipStream_t s);
 
+template <typename T>
 int fused_chunk(const Grid& g, int num_cu);
 
 template <typename T>

@@ -28,13 +28,14 @@
 
 namespace lesjet {
 
-constexpr int FB_X = 64;              // threads along i (ring-1 columns)
-constexpr int FB_Y = 8;               // threads along j
-constexpr int FT_X = FB_X - 2;        // interior outputs along i
-constexpr int FT_Y = FB_Y - 2;        // interior outputs along j
-constexpr int FR_X = FB_X + 2;        // ring-2 tile
-constexpr int FR_Y = FB_Y + 2;
-constexpr int NBORDER = FR_X * FR_Y - FB_X * FB_Y;   // ring-2 points without a thread
+// Tile shape per precision (threads along i and j of a ring-1 tile):
+// FP64 16 x 16 (LDS 59 KB, two blocks per CU), FP32 32 x 8 (LDS 30 KB, three
+// blocks per CU); both measured fastest among 64x8, 32x8 and 16x16 on the
+// jet meshes.
+template <typename T> struct Tile;
+template <> struct Tile<double> { static constexpr int X = 16, Y = 16, PER_CU = 2; };
+template <> struct Tile<float> { static constexpr int X = 32, Y = 8, PER_CU = 3; };
+
 constexpr int NPQ = 8;                // G(5), lambda_bar, nu, V per direction
 
 enum { EPI_R = 0, EPI_RK = 1, EPI_RK_LAST = 2 };
@@ -65,21 +66,49 @@ __device__ __forceinline__ void load_metrics(const T* __restrict__ M, const Grid
   }
 }
 
+// Workgroups are dealt to the eight XCDs (each with its own L2) in turn.  The
+// hardware id is remapped so that XCD x receives a contiguous run of tiles,
+// i fastest, then j, then the k-chunk: tiles that share halos run at the
+// same time on the same L2.
+constexpr int NXCD = 8;
+
+struct TileMap {
+  int gx, gy, gz;       // tiles along i, j and k-chunks
+  int per_xcd;          // ceil(gx gy gz / NXCD)
+};
+
+// Register budget: two waves per SIMD (FP64 uses all 256 VGPRs; constraining
+// FP32 to 128 for more waves costs spills and measured slower).
+template <typename T> struct FusedOcc { static constexpr int waves = 2; };
+
 template <typename T, int EPI>
-__global__ void __launch_bounds__(FB_X * FB_Y)
+__global__ void __launch_bounds__(Tile<T>::X * Tile<T>::Y, FusedOcc<T>::waves)
 k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, int kc,
-        T* out, const double* Q0, double* Q64, double alpha,
+        TileMap tm, T* out, const double* Q0, double* Q64, double alpha,
         const double* __restrict__ dtp, Phys<double> ph64, unsigned long long* __restrict__ maxbits) {
+  constexpr int FB_X = Tile<T>::X;              // threads along i (ring-1 columns)
+  constexpr int FB_Y = Tile<T>::Y;              // threads along j
+  constexpr int FT_X = FB_X - 2;                // interior outputs along i
+  constexpr int FT_Y = FB_Y - 2;                // interior outputs along j
+  constexpr int FR_X = FB_X + 2;                // ring-2 tile
+  constexpr int FR_Y = FB_Y + 2;
+  constexpr int NBORDER = FR_X * FR_Y - FB_X * FB_Y;   // ring-2 points without a thread
   __shared__ T sQ[5][FR_Y][FR_X];
   __shared__ T sP[5][FR_Y][FR_X];
   __shared__ T sX[NPQ][FB_Y][FB_X];
   __shared__ T sE[NPQ][FB_Y][FB_X];
-  __shared__ double sRed[FB_X * FB_Y / 64];
+  __shared__ double sRed[(FB_X * FB_Y + 63) / 64];
 
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * FB_X + tx;
-  const int i0 = blockIdx.x * FT_X, j0 = blockIdx.y * FT_Y;
-  const int k0 = blockIdx.z * kc;
+  const int hw = blockIdx.x;
+  const int tile = (hw % NXCD) * tm.per_xcd + hw / NXCD;
+  if (tile >= tm.gx * tm.gy * tm.gz) return;          // uniform for the block
+  const int bx = tile % tm.gx;
+  const int by = (tile / tm.gx) % tm.gy;
+  const int bz = tile / (tm.gx * tm.gy);
+  const int i0 = bx * FT_X, j0 = by * FT_Y;
+  const int k0 = bz * kc;
   const int k1 = min(k0 + kc, g.nth);
   const int i = i0 - 1 + tx, j = j0 - 1 + ty;
   const bool col_ok = i >= -1 && i <= g.nx && j >= -1 && j <= g.nr;   // needed ring-1 column
@@ -134,25 +163,26 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
 #pragma unroll
   for (int c = 0; c < 5; ++c) { Wb[c] = Wa[c]; Gz[c] = 0; acc[c] = 0; }
 
+  if (has_b) {                           // border of the first plane
+    T bq[5], bp[5];
+    load_q(Qin, g, bi, bj, k0 - 1, bq);
+    prim5(bq, ph, bp);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      sQ[c][bry][brx] = bq[c];
+      sP[c][bry][brx] = bp[c];
+    }
+  }
+
   for (int kk = k0 - 1; kk <= k1; ++kk) {
     const bool more = kk < k1;
-    // issue the loads of the next planes first
+    // own-column and metric loads of the next plane, in flight during (b)
     if (more) {
       if (kk + 2 <= k1 + 1) load_q(Qin, g, i, j, kk + 2, Qn);
       load_metrics(M, g, i, j, kk + 1, col_ok, metn);
     }
-    // (a) plane kk into LDS: the ring-2 border (the own column was written at
-    // the end of the previous iteration)
-    if (has_b) {
-      T bq[5], bp[5];
-      load_q(Qin, g, bi, bj, kk, bq);
-      prim5(bq, ph, bp);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        sQ[c][bry][brx] = bq[c];
-        sP[c][bry][brx] = bp[c];
-      }
-    }
+    // (a) plane kk is in LDS (written before the loop or at the end of the
+    // previous iteration)
     __syncthreads();
 
     // (b) point quantities at (i, j, kk)
@@ -190,6 +220,9 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     sE[5][ty][tx] = po.lb[1];
     sE[6][ty][tx] = po.nu[1];
     sE[7][ty][tx] = in.V;
+    // border of the next plane, in flight during the face phase
+    T Bn[5];
+    if (more && has_b) load_q(Qin, g, bi, bj, kk + 1, Bn);
     __syncthreads();
 
     // (c) faces of the interior columns
@@ -197,50 +230,52 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
       // in-plane faces (output planes only); W = Q with E replaced by E + p
       T rhs[5] = {0, 0, 0, 0, 0};
       if (kk < k1) {
-        T W5[5][5];
+        // sliding window along each in-plane direction: the face -1/2 uses
+        // points -2..1, the face +1/2 points -1..2
+        T Wm[5], Wl[5], Wr[5], Wp[5], Fm[5], Fp[5];
+        auto wload = [&](int yy, int xx, T w[5]) {
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
+          for (int c = 0; c < 4; ++c) w[c] = sQ[c][yy][xx];
+          w[4] = sQ[4][yy][xx] + sP[4][yy][xx];
+        };
+        {
+          T GA[5], GB[5];
+          wload(ty + 1, tx - 1, Wm); wload(ty + 1, tx, Wl); wload(ty + 1, tx + 1, Wr);
+          wload(ty + 1, tx + 2, Wp);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) W5[m][c] = sQ[c][ty + 1][tx - 1 + m];
-          W5[m][4] = sQ[4][ty + 1][tx - 1 + m] + sP[4][ty + 1][tx - 1 + m];
+          for (int c = 0; c < 5; ++c) { GA[c] = sX[c][ty][tx - 1]; GB[c] = sX[c][ty][tx]; }
+          face_flux(GA, GB, sX[5][ty][tx - 1], sX[5][ty][tx], sX[6][ty][tx - 1], sX[6][ty][tx],
+                    sX[7][ty][tx - 1], sX[7][ty][tx], Wm, Wl, Wr, Wp, phys_im, ph, Fm);
+          wload(ty + 1, tx + 3, Wm);       // reuse Wm as the point +2
+#pragma unroll
+          for (int c = 0; c < 5; ++c) GA[c] = sX[c][ty][tx + 1];
+          face_flux(GB, GA, sX[5][ty][tx], sX[5][ty][tx + 1], sX[6][ty][tx], sX[6][ty][tx + 1],
+                    sX[7][ty][tx], sX[7][ty][tx + 1], Wl, Wr, Wp, Wm, phys_ip, ph, Fp);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) rhs[c] = Fp[c] - Fm[c];
         }
-        T GL[5], GC[5], GR[5], Fm[5], Fp[5];
+        {
+          T GA[5], GB[5];
+          wload(ty - 1, tx + 1, Wm); wload(ty, tx + 1, Wl); wload(ty + 1, tx + 1, Wr);
+          wload(ty + 2, tx + 1, Wp);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          GL[c] = sX[c][ty][tx - 1];
-          GC[c] = sX[c][ty][tx];
-          GR[c] = sX[c][ty][tx + 1];
+          for (int c = 0; c < 5; ++c) { GA[c] = sE[c][ty - 1][tx]; GB[c] = sE[c][ty][tx]; }
+          face_flux(GA, GB, sE[5][ty - 1][tx], sE[5][ty][tx], sE[6][ty - 1][tx], sE[6][ty][tx],
+                    sE[7][ty - 1][tx], sE[7][ty][tx], Wm, Wl, Wr, Wp, phys_jm, ph, Fm);
+          wload(ty + 3, tx + 1, Wm);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) GA[c] = sE[c][ty + 1][tx];
+          face_flux(GB, GA, sE[5][ty][tx], sE[5][ty + 1][tx], sE[6][ty][tx], sE[6][ty + 1][tx],
+                    sE[7][ty][tx], sE[7][ty + 1][tx], Wl, Wr, Wp, Wm, phys_jp, ph, Fp);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) rhs[c] += Fp[c] - Fm[c];
         }
-        face_flux(GL, GC, sX[5][ty][tx - 1], sX[5][ty][tx], sX[6][ty][tx - 1], sX[6][ty][tx],
-                  sX[7][ty][tx - 1], sX[7][ty][tx], W5[0], W5[1], W5[2], W5[3], phys_im, ph, Fm);
-        face_flux(GC, GR, sX[5][ty][tx], sX[5][ty][tx + 1], sX[6][ty][tx], sX[6][ty][tx + 1],
-                  sX[7][ty][tx], sX[7][ty][tx + 1], W5[1], W5[2], W5[3], W5[4], phys_ip, ph, Fp);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) rhs[c] = Fp[c] - Fm[c];
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) W5[m][c] = sQ[c][ty - 1 + m][tx + 1];
-          W5[m][4] = sQ[4][ty - 1 + m][tx + 1] + sP[4][ty - 1 + m][tx + 1];
-        }
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          GL[c] = sE[c][ty - 1][tx];
-          GC[c] = sE[c][ty][tx];
-          GR[c] = sE[c][ty + 1][tx];
-        }
-        face_flux(GL, GC, sE[5][ty - 1][tx], sE[5][ty][tx], sE[6][ty - 1][tx], sE[6][ty][tx],
-                  sE[7][ty - 1][tx], sE[7][ty][tx], W5[0], W5[1], W5[2], W5[3], phys_jm, ph, Fm);
-        face_flux(GC, GR, sE[5][ty][tx], sE[5][ty + 1][tx], sE[6][ty][tx], sE[6][ty + 1][tx],
-                  sE[7][ty][tx], sE[7][ty + 1][tx], W5[1], W5[2], W5[3], W5[4], phys_jp, ph, Fp);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) rhs[c] += Fp[c] - Fm[c];
       }
       // zeta face kk-1/2: L = kk-1 (registers), R = kk
       T Wc[5], Wd[5], Fk[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) { Wc[c] = in.q[c]; Wd[c] = Qd[c]; }
-      Wc[4] += in.pr[4];
+      for (int c = 0; c < 5; ++c) { Wc[c] = sQ[c][ty + 1][tx + 1]; Wd[c] = Qd[c]; }
+      Wc[4] += sP[4][ty + 1][tx + 1];
       Wd[4] += Pd[4];
       face_flux(Gz, po.G[2], lbz, po.lb[2], nuz, po.nu[2], Vz, in.V, Wa, Wb, Wc, Wd, false, ph, Fk);
       if (kk - 1 >= k0) {
@@ -282,21 +317,30 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     for (int c = 0; c < 5; ++c) {
       Gz[c] = po.G[2][c];
       Wa[c] = Wb[c];
-      Wb[c] = in.q[c];
-      Pb[c] = in.pr[c];
+      Wb[c] = sQ[c][ty + 1][tx + 1];     // own state of plane kk, re-read from LDS
+      Pb[c] = sP[c][ty + 1][tx + 1];
     }
-    Wb[4] += in.pr[4];
+    Wb[4] += Pb[4];
     lbz = po.lb[2];
     nuz = po.nu[2];
     Vz = in.V;
     __syncthreads();
     if (more) {
-      // plane kk+1 of the own column goes straight to LDS
+      // plane kk+1 goes to LDS: own column and ring-2 border
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         sQ[c][ty + 1][tx + 1] = Qd[c];
         sP[c][ty + 1][tx + 1] = Pd[c];
         Qd[c] = Qn[c];
+      }
+      if (has_b) {
+        T bp[5];
+        prim5(Bn, ph, bp);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          sQ[c][bry][brx] = Bn[c];
+          sP[c][bry][brx] = bp[c];
+        }
       }
       prim5(Qd, ph, Pd);
 #pragma unroll
@@ -315,14 +359,17 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     __syncthreads();
     if (tid == 0) {
       double b = sRed[0];
-      for (int w = 1; w < FB_X * FB_Y / 64; ++w)
+      for (int w = 1; w < (FB_X * FB_Y + 63) / 64; ++w)
         if (sRed[w] != sRed[w] || sRed[w] > b) b = sRed[w];
       atomicMax(maxbits, (unsigned long long)__double_as_longlong(b));
     }
   }
 }
 
+template <typename T>
 int fused_chunk(const Grid& g, int num_cu) {
+  constexpr int FT_X = Tile<T>::X - 2, FT_Y = Tile<T>::Y - 2;
+  num_cu *= Tile<T>::PER_CU;          // resident blocks
   const long long tiles = (long long)((g.nx + FT_X - 1) / FT_X) * ((g.nr + FT_Y - 1) / FT_Y);
   // pick the chunk length that minimises (rounds of resident blocks) x (planes per block)
   int best = g.nth;
@@ -340,20 +387,29 @@ template <typename T>
 hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, int kc, int epi,
                         T* out, const double* Q0, double* Q64, double alpha, const double* dt,
                         const Phys<double>& ph64, unsigned long long* maxbits, hipStream_t s) {
-  const dim3 grid((g.nx + FT_X - 1) / FT_X, (g.nr + FT_Y - 1) / FT_Y, (g.nth + kc - 1) / kc);
-  const dim3 block(FB_X, FB_Y, 1);
+  constexpr int FT_X = Tile<T>::X - 2, FT_Y = Tile<T>::Y - 2;
+  TileMap tm;
+  tm.gx = (g.nx + FT_X - 1) / FT_X;
+  tm.gy = (g.nr + FT_Y - 1) / FT_Y;
+  tm.gz = (g.nth + kc - 1) / kc;
+  const long long ntiles = (long long)tm.gx * tm.gy * tm.gz;
+  tm.per_xcd = (int)((ntiles + NXCD - 1) / NXCD);
+  const dim3 grid((unsigned)(tm.per_xcd * NXCD));
+  const dim3 block(Tile<T>::X, Tile<T>::Y, 1);
   if (epi == EPI_R)
-    hipLaunchKernelGGL((k_fused<T, EPI_R>), grid, block, 0, s, Q, M, g, ph, kc, out, Q0, Q64,
+    hipLaunchKernelGGL((k_fused<T, EPI_R>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0, Q64,
                        alpha, dt, ph64, maxbits);
   else if (epi == EPI_RK)
-    hipLaunchKernelGGL((k_fused<T, EPI_RK>), grid, block, 0, s, Q, M, g, ph, kc, out, Q0, Q64,
+    hipLaunchKernelGGL((k_fused<T, EPI_RK>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0, Q64,
                        alpha, dt, ph64, maxbits);
   else
-    hipLaunchKernelGGL((k_fused<T, EPI_RK_LAST>), grid, block, 0, s, Q, M, g, ph, kc, out, Q0,
+    hipLaunchKernelGGL((k_fused<T, EPI_RK_LAST>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0,
                        Q64, alpha, dt, ph64, maxbits);
   return hipGetLastError();
 }
 
+template int fused_chunk<double>(const Grid&, int);
+template int fused_chunk<float>(const Grid&, int);
 template hipError_t launch_fused<double>(const double*, const double*, const Grid&,
                                          const Phys<double>&, int, int, double*, const double*,
                                          double*, double, const double*, const Phys<double>&,

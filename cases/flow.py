@@ -21,9 +21,11 @@ GAMMA = 1.4
 
 # random-field ids (top byte of the counter key); one per independent field
 FIELD_BOX = {"rho": 1, "u": 2, "v": 3, "w": 4, "p": 5}
-FIELD_JET_IC = {"u": 11, "v": 12, "w": 13}
-FIELD_JET_IN = {"u": 21, "v": 22, "w": 23}
-FIELD_COTANGENT = 31
+FIELD_JET_IC = {"u": 11, "v": 12, "w": 13, "rho": 14, "p": 15}
+FIELD_JET_IN = {"u": 21, "v": 22, "w": 23, "rho": 24, "p": 25}
+FIELD_COTANGENT = 31      # cotangents (output-side seeds of adjoint checks)
+FIELD_DIRECTION = 32      # perturbation directions (input side)
+FIELD_DIRECTION_IN = 33   # perturbation directions of the inflow data
 
 
 def conserved(rho, u, v, w, p, gamma=GAMMA):
@@ -108,10 +110,12 @@ def jet_axial_velocity(R, TH, coef=None):
 
 
 def jet_state(X, R, TH, seed=2, coef=None, noise=1e-3 * JET_UJ, k0=0, k1=None,
-              gamma=GAMMA, device="cpu"):
+              gamma=GAMMA, device="cpu", thermo_noise=0.0):
     """Parallel-jet initial state: the inflow profile extended uniformly in x,
     rho = 1, p = 1/gamma, plus seeded velocity noise on u, v, w.
 
+    thermo_noise > 0 also multiplies rho and p by 1 + thermo_noise U(-1, 1)
+    (a state with no uniform-pressure degeneracy, for derivative checks).
     Planes k0..k1 only (for chunked generation of large meshes)."""
     nth_all = TH.numel()
     if k1 is None:
@@ -132,13 +136,18 @@ def jet_state(X, R, TH, seed=2, coef=None, noise=1e-3 * JET_UJ, k0=0, k1=None,
         w = w + noise * rng.symmetric(seed, FIELD_JET_IC["w"], idx)
     rho = torch.ones_like(v)
     p = torch.full_like(v, 1.0 / gamma)
+    if thermo_noise:
+        idx = interior_index((nk, nr, nx), k0, device=device)
+        rho = rho * (1.0 + thermo_noise * rng.symmetric(seed, FIELD_JET_IC["rho"], idx))
+        p = p * (1.0 + thermo_noise * rng.symmetric(seed, FIELD_JET_IC["p"], idx))
     return conserved(rho, u, v, w, p, gamma)
 
 
 def jet_inflow(R, TH, seed=2, coef=None, noise=1e-3 * JET_UJ, gamma=GAMMA,
-               device="cpu"):
+               device="cpu", thermo_noise=0.0):
     """Inflow target primitives (rho, u, v, w, p) at the entrance plane,
-    shaped (5, nth, nr): the jet profile plus a frozen seeded noise pattern."""
+    shaped (5, nth, nr): the jet profile plus a frozen seeded noise pattern
+    (and relative rho, p noise when thermo_noise > 0)."""
     R, TH = R.to(device), TH.to(device)
     if coef is not None:
         coef = coef.to(device)
@@ -155,6 +164,12 @@ def jet_inflow(R, TH, seed=2, coef=None, noise=1e-3 * JET_UJ, gamma=GAMMA,
         w = w + noise * rng.symmetric(seed, FIELD_JET_IN["w"], idx)
     rho = torch.ones_like(u)
     p = torch.full_like(u, 1.0 / gamma)
+    if thermo_noise:
+        k = torch.arange(nth, dtype=torch.int64, device=device).view(nth, 1)
+        j = torch.arange(nr, dtype=torch.int64, device=device).view(1, nr)
+        idx = k * nr + j
+        rho = rho * (1.0 + thermo_noise * rng.symmetric(seed, FIELD_JET_IN["rho"], idx))
+        p = p * (1.0 + thermo_noise * rng.symmetric(seed, FIELD_JET_IN["p"], idx))
     return torch.stack([rho, u, v, w, p])
 
 

@@ -12,7 +12,7 @@ import math
 
 import torch
 
-from . import flow, mesh
+from . import flow, mesh, rng
 
 RK_ALPHA = (1.0 / 4.0, 1.0 / 6.0, 3.0 / 8.0, 1.0 / 2.0, 1.0)   # Jameson 5-stage
 
@@ -67,14 +67,27 @@ def jet_grid(nx, nr, nth):
 
 
 def jet_problem(nx, nr, nth, seed=2, coef=None, noise=1e-3 * flow.JET_UJ,
-                with_xyz=True, device="cpu"):
+                with_xyz=True, device="cpu", thermo_noise=0.0):
     """Cylindrical jet mesh with the Mach-1.4 parallel-jet state."""
     X, R, TH = jet_grid(nx, nr, nth)
     xyz = mesh.cylindrical_coords(X, R, TH, device=device) if with_xyz else None
-    Q = flow.jet_state(X, R, TH, seed=seed, coef=coef, noise=noise, device=device)
-    inflow = flow.jet_inflow(R, TH, seed=seed, coef=coef, noise=noise, device=device)
+    Q = flow.jet_state(X, R, TH, seed=seed, coef=coef, noise=noise, device=device,
+                       thermo_noise=thermo_noise)
+    inflow = flow.jet_inflow(R, TH, seed=seed, coef=coef, noise=noise, device=device,
+                             thermo_noise=thermo_noise)
     return dict(name=f"jet{nx}x{nr}x{nth}", xyz=xyz, Q=Q, inflow=inflow,
                 params=jet_params(), grid=(X, R, TH))
+
+
+def seeded_field(shape, seed, field, kind="gaussian", device="cpu"):
+    """A seeded random array of `shape` (cotangents and perturbation
+    directions of derivative checks), indexed by the row-major position."""
+    n = 1
+    for s in shape:
+        n *= s
+    idx = torch.arange(n, dtype=torch.int64, device=device)
+    draw = rng.gaussian if kind == "gaussian" else rng.symmetric
+    return draw(seed, field, idx).view(*shape)
 
 
 # the configurations the measurements and parity tests are run on

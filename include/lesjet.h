@@ -174,6 +174,51 @@ int les_residual_reference(les_ctx* c, void* Q, void* R, void* stream);
 int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed,
                  double* dt_out, void* stream);
 
+/* Adjoint of the residual (FP64 precision only; LES_EUNSUPPORTED otherwise):
+ *   Qbar = (dR/dQ)^T Rbar,
+ * the vector-Jacobian product of R (section "Spatial Discretization") as a
+ * function of the interior of Q, the ghost fill of section "Boundary
+ * Conditions" included, with the boundary data (entrance target, far-field
+ * state, back pressure) held fixed.
+ *   Q          device, FP64, padded, 5 variables; its ghost entries are
+ *              overwritten by the ghost fill, the interior is read only.
+ *   Rbar       device, same layout; only interior entries are read.
+ *   Qbar       device, same layout, overwritten: interior = the cotangent,
+ *              ghost entries and pitch padding = 0.  May alias Rbar.
+ *   inflow_bar device, (5, nth, nr) doubles, or NULL: the cotangent of the
+ *              entrance target (rho, u, v, w, p) is ADDED to it (only when
+ *              xi- is an entrance).
+ * Gather form without floating-point atomics: results are bitwise
+ * reproducible.  Holds 72 scratch variables of the padded layout after the
+ * first call.  Asynchronous on `stream`. */
+int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, double* inflow_bar,
+                     void* stream);
+
+/* Adjoint of one RK5 step with a fixed dt > 0 (section "Time Marching
+ * Method"; a CFL step is frozen at its value): given the cotangent
+ * Qbar_np1 of Q^(n+1), writes that of Q^n,
+ *   b5 = Qbar_np1,  b(l-1) = -alpha_l dt (dR/dQ)^T(Q^(l-1)) b(l),
+ *   Qbar_n = b5 + b4 + b3 + b2 + b1 + b0,
+ * recomputing the stage states Q^(1..4) from Qn with the les_rk5_step
+ * kernels.  Qn as in les_rk5_step (ghosts overwritten, interior unchanged);
+ * ghost entries of Qbar_np1 are ignored, those of Qbar_n are zero;
+ * Qbar_n may alias Qbar_np1; inflow_bar as in les_residual_vjp (added to).
+ * FP64 only.  Holds 25 more padded variables after the first call.
+ * Asynchronous on `stream`. */
+int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, double* Qbar_n,
+                     double* inflow_bar, void* stream);
+
+/* Diagnostics of the FP64 state Qn (device, padded), in a fixed summation
+ * order (bitwise reproducible):
+ *   totals (device, 5 doubles, or NULL): sum over the interior of J^-1 Q_c,
+ *     the discrete conserved totals (constant on a periodic mesh);
+ *   sum1, sum2 (device, (5, nr, nx) doubles each, or NULL): incremented by
+ *     sum over k of phi and phi^2, phi = (rho, u, v, w, p), the accumulators
+ *     of azimuthal and temporal mean and rms fields (the caller zeroes them).
+ * Asynchronous on `stream`. */
+int les_diagnostics(les_ctx* c, const double* Qn, double* totals, double* sum1, double* sum2,
+                    void* stream);
+
 /* Measurement support.  While enabled, every launch of the residual stage
  * kernel issued by les_residual and les_rk5_step is bracketed by a pair of
  * HIP events recorded on the call's stream, so the durations are those of

@@ -21,7 +21,7 @@ LIB = os.path.join(LIBDIR, "liblesjet.so")
 ARCH = os.environ.get("LESJET_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "geometry.hip", "ghost.hip", "residual_ref.hip", "residual_fused.hip",
-           "rk.hip"]
+           "rk.hip", "diag.hip", "adjoint.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -52,6 +52,22 @@ def _compile(src, build_dir=BUILD, defines=()):
     return obj, r.stderr
 
 
+CHECKS_SRC = os.path.join(ROOT, "tests", "host_checks.hip")
+CHECKS_LIB = os.path.join(LIBDIR, "liblesjet_checks.so")
+
+
+def build_checks():
+    """Host-compiled check library of the device functions (test helper)."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    tmp = CHECKS_LIB + ".tmp"
+    cmd = [_hipcc(), *CFLAGS, "-shared", "-x", "hip", CHECKS_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on host_checks.hip:\n{r.stderr[-6000:]}")
+    os.replace(tmp, CHECKS_LIB)
+    return CHECKS_LIB
+
+
 def build(verbose=False, lib=LIB, defines=()):
     """Compile all sources and link `lib`; `defines` are extra -D macros
     (variants for measurements, built to another path)."""
@@ -66,11 +82,14 @@ def build(verbose=False, lib=LIB, defines=()):
             if err.strip():
                 print(err, file=sys.stderr)
     tmp = lib + ".tmp"
-    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs]
+    cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-Wl,--no-undefined", "-o", tmp,
+           *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")
     os.replace(tmp, lib)
+    if lib == LIB and os.path.exists(CHECKS_SRC):
+        build_checks()
     return lib
 
 

@@ -29,6 +29,9 @@ struct les_ctx {
   void* stage[2] = {nullptr, nullptr};   // RK stage states (storage type)
   void* R = nullptr;           // residual buffer (storage type)
   void* PT = nullptr;          // point-quantity scratch of the two-pass residual
+  double* part = nullptr;      // per-block partial sums of the diagnostics
+  double* adj = nullptr;       // residual-adjoint scratch (VJP_SCRATCH_VARS variables, FP64)
+  double* adj_stage = nullptr; // RK5-step adjoint: stage states 1..4 and one cotangent (25 vars)
   unsigned long long* maxbits = nullptr;
   double* dt = nullptr;
   int* flag = nullptr;
@@ -173,12 +176,14 @@ static size_t storage_size(const les_params* p) {
 
 static void free_all(les_ctx* c) {
   void* ptrs[] = {c->coords, c->M, c->inflow, c->stage[0], c->stage[1], c->R, c->PT,
-                  c->maxbits, c->dt, c->flag};
+                  c->part, c->adj, c->adj_stage, c->maxbits, c->dt, c->flag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   c->coords = nullptr; c->M = nullptr; c->inflow = nullptr;
   c->stage[0] = c->stage[1] = nullptr;
-  c->R = nullptr; c->PT = nullptr; c->maxbits = nullptr; c->dt = nullptr; c->flag = nullptr;
+  c->R = nullptr; c->PT = nullptr; c->part = nullptr;
+  c->adj = nullptr; c->adj_stage = nullptr;
+  c->maxbits = nullptr; c->dt = nullptr; c->flag = nullptr;
 }
 
 static int dalloc(les_ctx* c, void** ptr, size_t bytes, const char* what) {
@@ -464,6 +469,104 @@ int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed, double
   hipStream_t s = (hipStream_t)stream;
   if (c->p.precision == LES_FP32_STORAGE) return rk5_steps<float>(c, Qn, nsteps, dt_fixed, dt_out, s);
   return rk5_steps<double>(c, Qn, nsteps, dt_fixed, dt_out, s);
+}
+
+int les_diagnostics(les_ctx* c, const double* Qn, double* totals, double* sum1, double* sum2,
+                    void* stream) {
+  int r = ready(c);
+  if (r != LES_OK) return r;
+  if (!Qn) return fail(c, LES_EINVAL, "Qn is NULL");
+  if (totals) {
+    r = dalloc(c, (void**)&c->part, (size_t)5 * diag_partials(c->g) * sizeof(double), "partials");
+    if (r != LES_OK) return r;
+  }
+  hipError_t e;
+  if (c->p.precision == LES_FP32_STORAGE)
+    e = launch_diagnostics<float>(Qn, (const float*)c->M, c->g, c->ph64, c->part, totals, sum1,
+                                  sum2, (hipStream_t)stream);
+  else
+    e = launch_diagnostics<double>(Qn, (const double*)c->M, c->g, c->ph64, c->part, totals, sum1,
+                                   sum2, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics kernels");
+  return LES_OK;
+}
+
+// Qb = (dR/dQ)^T Rb at Q (ghosts of Q filled here); inflow_bar accumulated.
+static int residual_vjp_into(les_ctx* c, double* Q, const double* Rb, double* Qb,
+                             double* inflow_bar, hipStream_t s) {
+  int r = dalloc(c, (void**)&c->adj, (size_t)VJP_SCRATCH_VARS * c->g.vs * sizeof(double),
+                 "adjoint scratch");
+  if (r != LES_OK) return r;
+  hipError_t e = ghosts<double>(c, Q, s);
+  if (e == hipSuccess) {
+    const long long v = c->g.vs;
+    e = launch_residual_vjp(Q, (const double*)c->M, c->g, c->ph64, c->p.bc, c->p.ref_prim,
+                            c->p.p_exit, c->inflow, Rb, c->adj, c->adj + 21 * v, c->adj + 47 * v,
+                            Qb, c->p.bc[0] == LES_BC_INFLOW ? inflow_bar : nullptr, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "residual adjoint kernels");
+  return LES_OK;
+}
+
+static int adjoint_ready(les_ctx* c) {
+  int r = ready(c);
+  if (r != LES_OK) return r;
+  if (c->p.precision != LES_FP64)
+    return fail(c, LES_EUNSUPPORTED, "the adjoint is available for the FP64 precision only");
+  return LES_OK;
+}
+
+int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, double* inflow_bar,
+                     void* stream) {
+  int r = adjoint_ready(c);
+  if (r != LES_OK) return r;
+  if (!Q || !Rbar || !Qbar) return fail(c, LES_EINVAL, "Q, Rbar or Qbar is NULL");
+  if (Q == Qbar || Q == Rbar) return fail(c, LES_EINVAL, "Q must not alias Rbar or Qbar");
+  return residual_vjp_into(c, Q, Rbar, Qbar, inflow_bar, (hipStream_t)stream);
+}
+
+int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, double* Qbar_n,
+                     double* inflow_bar, void* stream) {
+  int r = adjoint_ready(c);
+  if (r != LES_OK) return r;
+  if (!Qn || !Qbar_np1 || !Qbar_n) return fail(c, LES_EINVAL, "Qn, Qbar_np1 or Qbar_n is NULL");
+  if (Qn == Qbar_np1 || Qn == Qbar_n) return fail(c, LES_EINVAL, "Qn must not alias a cotangent");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(c, LES_EINVAL, "dt must be finite and > 0");
+  const long long v5 = 5LL * c->g.vs;
+  r = dalloc(c, (void**)&c->adj_stage, (size_t)5 * v5 * sizeof(double), "adjoint stage states");
+  if (r != LES_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  // forward: the stage states Q^(0) = Q^n, Q^(1..4) with the fixed dt, by the
+  // same kernels as les_rk5_step
+  double* X[5] = {Qn, c->adj_stage, c->adj_stage + v5, c->adj_stage + 2 * v5,
+                  c->adj_stage + 3 * v5};
+  double* B = c->adj_stage + 4 * v5;
+  const double* al = c->p.rk_alpha;
+  hipError_t e = launch_reset(c->maxbits, c->flag, s);
+  if (e == hipSuccess) e = launch_dt_finalize(c->maxbits, c->p.cfl, dt, c->dt, nullptr, c->flag, s);
+  for (int l = 1; l <= 4 && e == hipSuccess; ++l) {
+    e = ghosts<double>(c, X[l - 1], s);
+    if (e == hipSuccess)
+      e = launch_fused<double>(X[l - 1], (const double*)c->M, c->g, c->ph64, c->kc, FUSED_EPI_RK,
+                               X[l], Qn, nullptr, al[l - 1], c->dt, c->ph64, c->maxbits, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "rk5 adjoint forward kernels");
+  // reverse: b5 = Qbar^(n+1); b(l-1) = -alpha_l dt J(Q^(l-1))^T b(l);
+  // Qbar^n = b5 + b4 + ... + b0
+  e = launch_scale(Qbar_np1, -al[4] * dt, B, v5, s);
+  if (e == hipSuccess) e = launch_interior_copy(Qbar_np1, Qbar_n, c->g, s);
+  if (e != hipSuccess) return hip_fail(c, e, "rk5 adjoint kernels");
+  for (int l = 5; l >= 1; --l) {
+    if (l < 5) {
+      e = launch_scale(B, -al[l - 1] * dt, B, v5, s);
+      if (e != hipSuccess) return hip_fail(c, e, "rk5 adjoint kernels");
+    }
+    r = residual_vjp_into(c, X[l - 1], B, B, inflow_bar, s);
+    if (r != LES_OK) return r;
+    e = launch_accumulate(B, Qbar_n, v5, s);
+    if (e != hipSuccess) return hip_fail(c, e, "rk5 adjoint kernels");
+  }
+  return LES_OK;
 }
 
 int les_profile(les_ctx* c, int32_t enable) {

@@ -9,8 +9,8 @@
 //   eta+ periodic | far field: Riemann invariants with the reference state;
 //   zeta periodic.
 // Both ghost layers of a non-periodic face receive the same face state.
+#include "bc.hpp"
 #include "launch.hpp"
-#include "physics.hpp"
 
 namespace lesjet {
 
@@ -24,20 +24,23 @@ __device__ __forceinline__ void store5(T* Q, int vs, int o, const T q[5]) {
 #pragma unroll
   for (int c = 0; c < 5; ++c) Q[(long long)c * vs + o] = q[c];
 }
+// Unit normal S^d / |S^d| (times sgn) at offset o, in FP64 for the
+// boundary formulas.
 template <typename T>
-__device__ __forceinline__ void unit_normal(const T* M, int vs, int o, int d, T sgn, T n[3]) {
-  const T a = M[(long long)(3 * d + 0) * vs + o];
-  const T b = M[(long long)(3 * d + 1) * vs + o];
-  const T c = M[(long long)(3 * d + 2) * vs + o];
-  const T inv = sgn / tsqrt(a * a + b * b + c * c);
+__device__ __forceinline__ void unit_normal(const T* M, int vs, int o, int d, double sgn,
+                                            double n[3]) {
+  const double a = (double)M[(long long)(3 * d + 0) * vs + o];
+  const double b = (double)M[(long long)(3 * d + 1) * vs + o];
+  const double c = (double)M[(long long)(3 * d + 2) * vs + o];
+  const double inv = sgn / sqrt(a * a + b * b + c * c);
   n[0] = a * inv; n[1] = b * inv; n[2] = c * inv;
 }
 
 // xi faces, one thread per (j, k) of the interior.
 template <typename T>
 __global__ void k_ghost_xi(T* __restrict__ Q, Grid g, const T* __restrict__ M,
-                           const double* __restrict__ inflow, Phys<T> ph, int lo_kind,
-                           int hi_kind, T p_exit) {
+                           const double* __restrict__ inflow, double gamma, int lo_kind,
+                           int hi_kind, double p_exit) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.nr * g.nth) return;
   const int j = t % g.nr, k = t / g.nr;
@@ -51,26 +54,16 @@ __global__ void k_ghost_xi(T* __restrict__ Q, Grid g, const T* __restrict__ M,
     const int oe = g.at(0, j, k);
     T qe[5];
     load5(Q, g.vs, oe, qe);
-    T n[3];
-    unit_normal(M, g.vs, oe, 0, T(-1), n);
-    Prim<T> tg;
+    double n[3];
+    unit_normal(M, g.vs, oe, 0, -1.0, n);
+    BPrim<T> tg;
     const long long sp = (long long)g.nth * g.nr, it = (long long)k * g.nr + j;
     tg.rho = (T)inflow[0 * sp + it];
     tg.u = (T)inflow[1 * sp + it];
     tg.v = (T)inflow[2 * sp + it];
     tg.w = (T)inflow[3 * sp + it];
     tg.p = (T)inflow[4 * sp + it];
-    const T at = tsqrt(ph.gamma * tg.p / tg.rho);
-    const T mn = -(tg.u * n[0] + tg.v * n[1] + tg.w * n[2]) / at;
-    if (mn >= T(1)) {
-      conserved(tg, ph, q);
-    } else {
-      Prim<T> f;
-      const int br = riemann(primitives(qe, ph), tg, n, ph, f);
-      if (br == 0) for (int c = 0; c < 5; ++c) q[c] = qe[c];
-      else if (br == 1) conserved(tg, ph, q);
-      else conserved(f, ph, q);
-    }
+    bc_inflow(qe, tg, n, gamma, q);
     for (int m = 1; m <= NG; ++m) store5(Q, g.vs, g.at(-m, j, k), q);
   }
   if (hi_kind == BC_PERIODIC) {
@@ -82,25 +75,17 @@ __global__ void k_ghost_xi(T* __restrict__ Q, Grid g, const T* __restrict__ M,
     const int oe = g.at(g.nx - 1, j, k);
     T qe[5];
     load5(Q, g.vs, oe, qe);
-    T n[3];
-    unit_normal(M, g.vs, oe, 0, T(1), n);
-    Prim<T> e = primitives(qe, ph);
-    const T ae = tsqrt(ph.gamma * e.p / e.rho);
-    const T qn = e.u * n[0] + e.v * n[1] + e.w * n[2];
-    if (qn / ae >= T(1)) {
-      for (int c = 0; c < 5; ++c) q[c] = qe[c];
-    } else {
-      e.p = p_exit;
-      conserved(e, ph, q);
-    }
+    double n[3];
+    unit_normal(M, g.vs, oe, 0, 1.0, n);
+    bc_outflow(qe, n, gamma, p_exit, q);
     for (int m = 1; m <= NG; ++m) store5(Q, g.vs, g.at(g.nx - 1 + m, j, k), q);
   }
 }
 
 // eta faces, one thread per (i, k), i over the padded range, k interior.
 template <typename T>
-__global__ void k_ghost_eta(T* __restrict__ Q, Grid g, const T* __restrict__ M, Phys<T> ph,
-                            int lo_kind, int hi_kind, Prim<T> ref) {
+__global__ void k_ghost_eta(T* __restrict__ Q, Grid g, const T* __restrict__ M, double gamma,
+                            int lo_kind, int hi_kind, BPrim<T> ref) {
   const int NX = g.nx + 2 * NG;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= NX * g.nth) return;
@@ -127,13 +112,9 @@ __global__ void k_ghost_eta(T* __restrict__ Q, Grid g, const T* __restrict__ M, 
     const int oe = g.at(i, g.nr - 1, k);
     T qe[5];
     load5(Q, g.vs, oe, qe);
-    T n[3];
-    unit_normal(M, g.vs, oe, 1, T(1), n);
-    Prim<T> f;
-    const int br = riemann(primitives(qe, ph), ref, n, ph, f);
-    if (br == 0) for (int c = 0; c < 5; ++c) q[c] = qe[c];
-    else if (br == 1) conserved(ref, ph, q);
-    else conserved(f, ph, q);
+    double n[3];
+    unit_normal(M, g.vs, oe, 1, 1.0, n);
+    bc_farfield(qe, ref, n, gamma, q);
     for (int m = 1; m <= NG; ++m) store5(Q, g.vs, g.at(i, g.nr - 1 + m, k), q);
   }
 }
@@ -159,13 +140,14 @@ hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
                          const Phys<T>& ph, const int bc[6], const double ref_prim[5],
                          double p_exit, hipStream_t s) {
   const int bs = 256;
+  const double gamma = (double)ph.gamma;
   hipLaunchKernelGGL(k_ghost_xi<T>, dim3(blocks_for((long long)g.nr * g.nth, bs)), dim3(bs), 0,
-                     s, Q, g, M, inflow, ph, bc[0], bc[1], (T)p_exit);
-  Prim<T> ref;
+                     s, Q, g, M, inflow, gamma, bc[0], bc[1], p_exit);
+  BPrim<T> ref;
   ref.rho = (T)ref_prim[0]; ref.u = (T)ref_prim[1]; ref.v = (T)ref_prim[2];
   ref.w = (T)ref_prim[3]; ref.p = (T)ref_prim[4];
   hipLaunchKernelGGL(k_ghost_eta<T>, dim3(blocks_for((long long)(g.nx + 2 * NG) * g.nth, bs)),
-                     dim3(bs), 0, s, Q, g, M, ph, bc[2], bc[3], ref);
+                     dim3(bs), 0, s, Q, g, M, gamma, bc[2], bc[3], ref);
   hipLaunchKernelGGL(k_ghost_zeta<T>,
                      dim3(blocks_for((long long)(g.nx + 2 * NG) * (g.nr + 2 * NG), bs)), dim3(bs),
                      0, s, Q, g);

@@ -44,6 +44,25 @@ template <typename T, typename TS>
 hipError_t launch_rk_update(const double* Q0, const T* R, TS* Qout, double* Q64out, const Grid& g,
                             double alpha, const double* dt, hipStream_t s);
 
+int diag_partials(const Grid& g);
+
+template <typename TM>
+hipError_t launch_diagnostics(const double* Q, const TM* M, const Grid& g, const Phys<double>& ph,
+                              double* part, double* totals, double* s1, double* s2, hipStream_t s);
+
+// Residual adjoint (FP64): Qb = (dR/dQ)^T Rb on the padded layout (ghost
+// entries zero); inflow_bar (5, nth, nr) accumulated when non-null.  Scratch
+// PT (21 variables), A2 (26), A3 (25); Q's ghosts must be filled.
+hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
+                               const Phys<double>& ph, const int bc[6], const double ref_prim[5],
+                               double p_exit, const double* inflow, const double* Rb, double* PT,
+                               double* A2, double* A3, double* Qb, double* inflow_bar,
+                               hipStream_t s);
+constexpr int VJP_SCRATCH_VARS = 21 + 26 + 25;
+hipError_t launch_scale(const double* x, double a, double* y, long long n, hipStream_t s);
+hipError_t launch_interior_copy(const double* x, double* y, const Grid& g, hipStream_t s);
+hipError_t launch_accumulate(const double* x, double* y, long long n, hipStream_t s);
+
 hipError_t launch_to_float(const double* a, float* b, long long n, hipStream_t s);
 
 }  // namespace lesjet

@@ -103,6 +103,7 @@ hipError_t launch_residual_ref(const T* Q, const T* M, const Grid& g, const Phys
                                T* R, hipStream_t s) {
   const long long n1 = (long long)(g.nx + 2) * (g.nr + 2) * (g.nth + 2);
   hipLaunchKernelGGL(k_point_pass<T>, dim3(blocks_for(n1, 256)), dim3(256), 0, s, Q, M, g, ph, PT);
+  if (!R) return hipGetLastError();   // point quantities only
   const long long n = (long long)g.nx * g.nr * g.nth;
   hipLaunchKernelGGL(k_face_pass<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, Q, M, g, ph, PT, R);
   return hipGetLastError();

@@ -102,6 +102,58 @@ class Solver:
                        _stream(self.device))
         return dt_out
 
+    def _check_fp64_state(self, Q):
+        assert Q.dtype == torch.float64 and tuple(Q.shape) == (5,) + self.dims and Q.is_contiguous()
+
+    def new_inflow_bar(self):
+        nx, nr, nth = self.shape
+        return torch.zeros((5, nth, nr), dtype=torch.float64, device=self.device)
+
+    def residual_vjp(self, Qp, Rbar, Qbar=None, inflow_bar=None):
+        """(dR/dQ)^T Rbar at the padded FP64 state Qp (ghost fill included);
+        the entrance-target cotangent is added to `inflow_bar` if given."""
+        self._check_fp64_state(Qp)
+        self._check_fp64_state(Rbar)
+        if Qbar is None:
+            Qbar = self.field(5, dtype=torch.float64)
+        self._check_fp64_state(Qbar)
+        B.les_residual_vjp(self.ctx, Qp.data_ptr(), Rbar.data_ptr(), Qbar.data_ptr(),
+                           inflow_bar.data_ptr() if inflow_bar is not None else None,
+                           _stream(self.device))
+        return Qbar
+
+    def rk5_step_vjp(self, Qn, dt, Qbar_np1, Qbar_n=None, inflow_bar=None):
+        """Cotangent of Q^n from that of Q^(n+1) for one RK5 step of fixed dt."""
+        self._check_fp64_state(Qn)
+        self._check_fp64_state(Qbar_np1)
+        if Qbar_n is None:
+            Qbar_n = self.field(5, dtype=torch.float64)
+        self._check_fp64_state(Qbar_n)
+        B.les_rk5_step_vjp(self.ctx, Qn.data_ptr(), float(dt), Qbar_np1.data_ptr(),
+                           Qbar_n.data_ptr(),
+                           inflow_bar.data_ptr() if inflow_bar is not None else None,
+                           _stream(self.device))
+        return Qbar_n
+
+    def diagnostics(self, Qn, stats=None):
+        """Conservation totals (5 doubles, device) of the padded FP64 state;
+        if `stats` = (sum1, sum2) of shape (5, nr, nx) is given, adds the
+        azimuthal sums of (rho, u, v, w, p) and their squares."""
+        assert Qn.dtype == torch.float64 and tuple(Qn.shape) == (5,) + self.dims and Qn.is_contiguous()
+        totals = torch.empty(5, dtype=torch.float64, device=self.device)
+        s1 = s2 = None
+        if stats is not None:
+            s1, s2 = stats
+        B.les_diagnostics(self.ctx, Qn.data_ptr(), totals.data_ptr(),
+                          s1.data_ptr() if s1 is not None else None,
+                          s2.data_ptr() if s2 is not None else None, _stream(self.device))
+        return totals
+
+    def new_stats(self):
+        nx, nr, _ = self.shape
+        z = lambda: torch.zeros((5, nr, nx), dtype=torch.float64, device=self.device)  # noqa: E731
+        return z(), z()
+
     def profile(self, enable=True):
         B.les_profile(self.ctx, enable)
 

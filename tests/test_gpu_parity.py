@@ -212,3 +212,32 @@ def test_fused_matches_two_pass_reference(shape):
     print(f"{shape}: fused vs reference {err:.3e}")
     assert err <= 1e-13
     s.close()
+
+
+def test_diagnostics_conservation_and_stats():
+    """Totals of J^-1 Q match the oracle's sums and stay constant over RK5
+    steps on the periodic box (telescoping fluxes); azimuthal sums match
+    NumPy; two runs are bitwise identical."""
+    announce("diagnostics", "box32")
+    pb = problems.box_problem(32)
+    geo, _ = _oracle(pb)
+    Q = pb["Q"].numpy()
+    V = les.interior(geo["V"])
+    ref = [math.fsum((V * Q[c]).ravel()) for c in range(5)]
+    s = make_solver(pb)
+    Qn = s.pad(pb["Q"].cuda(), dtype=torch.float64)
+    st = s.new_stats()
+    t0 = to_np(s.diagnostics(Qn, st))
+    t0b = to_np(s.diagnostics(Qn))
+    assert np.array_equal(t0, t0b)
+    for c in range(5):
+        assert abs(t0[c] - ref[c]) <= 1e-13 * max(abs(ref[c]), abs(ref[1]))
+    rho, u, v, w, p = les.primitives(Q, 1.4)
+    for c, f in enumerate((rho, u, v, w, p)):
+        assert np.allclose(to_np(st[0][c]), f.sum(axis=0), rtol=1e-13, atol=1e-13)
+        assert np.allclose(to_np(st[1][c]), (f * f).sum(axis=0), rtol=1e-13, atol=1e-13)
+    s.rk5_step(Qn, 5)
+    t1 = to_np(s.diagnostics(Qn))
+    for c in range(5):
+        assert abs(t1[c] - t0[c]) <= 1e-13 * max(abs(t0[c]), abs(t0[1]))
+    s.close()

@@ -19,7 +19,12 @@ The JSON line also carries
                taken on the current kernel sources, else null;
   cpu_baseline the CPU oracle (plain NumPy FP64, single thread) timed on a
                bounded sample of the same workload: one RK stage (ghost fill,
-               residual, update) over the whole mesh.
+               residual, update) over the whole mesh;
+  precision_forms  the same workload and step count in the other precision
+               form (FP32 storage with FP64 accumulation, or plain FP64);
+  adjoint      residual-adjoint calls per second (les_residual_vjp) on the
+               160 x 100 x 128 jet mesh, and their time over that of
+               les_residual on the same state.
 """
 import argparse
 import hashlib
@@ -53,19 +58,32 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def make_workload(name, device):
+def make_workload(name, device, chunk_points=64 * 2 ** 20):
+    """(params, xyz, fill, inflow) of a named workload on `device`; fill(Qi)
+    writes the initial state into the interior view Qi (5, nth, nr, nx) in
+    azimuthal chunks, so meshes of 1e9 points need no full-size temporaries."""
     import torch
     from cases import flow, mesh, problems
     cfg = problems.CONFIGS[name]
     if cfg["kind"] == "box":
         pb = problems.box_problem(cfg["n"], seed=cfg["seed"])
-        return pb["params"], pb["xyz"].to(device), pb["Q"].to(device), None
+        Q = pb["Q"].to(device)
+        return pb["params"], pb["xyz"].to(device), (lambda Qi: Qi.copy_(Q)), None
     nx, nr, nth = cfg["shape"]
     X, R, TH = problems.jet_grid(nx, nr, nth)
-    xyz = mesh.cylindrical_coords(X, R, TH, device=device)
-    Q = flow.jet_state(X, R, TH, seed=cfg["seed"], device=device)
+    kc = max(1, chunk_points // (nx * nr))
+    xyz = torch.empty((3, nth, nr, nx), dtype=torch.float64, device=device)
+    for k0 in range(0, nth, kc):
+        k1 = min(nth, k0 + kc)
+        xyz[:, k0:k1] = mesh.cylindrical_coords(X, R, TH, k0, k1, device=device)
+
+    def fill(Qi):
+        for k0 in range(0, nth, kc):
+            k1 = min(nth, k0 + kc)
+            Qi[:, k0:k1] = flow.jet_state(X, R, TH, seed=cfg["seed"], k0=k0, k1=k1, device=device)
+
     inflow = flow.jet_inflow(R, TH, seed=cfg["seed"], device=device)
-    return problems.jet_params(), xyz, Q, inflow
+    return problems.jet_params(), xyz, fill, inflow
 
 
 def cpu_baseline(name):
@@ -201,6 +219,8 @@ def main():
     ap.add_argument("--config", default="jet5.9M")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other-precision run and the adjoint timing")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only time a device copy of this many GiB (counter calibration)")
     ap.add_argument("--rocprof-summary", nargs=3, metavar=("CSV_DIR", "OUT", "COMMAND"),
@@ -224,7 +244,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2301_00817_amd.solver import Solver
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -233,42 +252,20 @@ def main():
         return
     from cases import problems
     kind = problems.CONFIGS[args.config]["kind"]
-    prm, xyz, Q, inflow = make_workload(args.config, dev)
-    s = Solver(prm, xyz, inflow, precision=args.precision, device=dev)
-    del xyz
-    nx, nr, nth = s.shape
+    r = time_rk(args.config, args.precision, args.steps, args.warmup, dev)
+    nx, nr, nth = r["shape"]
     npts = nx * nr * nth
-    Qn = s.pad(Q, dtype=torch.float64)
-    del Q
-    torch.cuda.synchronize()
-    print(f"[bench] {args.config} {nx}x{nr}x{nth} {args.precision}: warmup {args.warmup}",
-          file=sys.stderr, flush=True)
-    if args.warmup:
-        s.rk5_step(Qn, args.warmup)
-    torch.cuda.synchronize()
-
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    s.profile(True)
-    s.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dts = s.rk5_step(Qn, args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launches, kms = s.profile_read()
-    s.profile(False)
-    assert bool(torch.isfinite(s.interior(Qn)).all()), "state is not finite"
-
-    value = npts * 5 * args.steps / wall / 1e6
+    prm = r["params"]
+    value = npts * 5 * args.steps / r["wall"] / 1e6
     bytes_launch = STAGE_BYTES[args.precision] * npts
-    avg_ms = kms / max(launches, 1)
+    avg_ms = r["kernel_ms"] / max(r["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     workload = f"{args.config}-{args.precision}"
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic_for(DOMINANT_KERNEL, workload, bytes_launch),
             "kernel": DOMINANT_KERNEL, "avg_launch_ms": round(avg_ms, 4),
-            "launches": launches, "algorithmic_bytes_per_launch": bytes_launch}
+            "launches": r["launches"], "algorithmic_bytes_per_launch": bytes_launch}
 
     out = {
         "metric": "Mpoint-RK-stage updates/s",
@@ -277,7 +274,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "ms_per_step": round(r["wall"] / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -287,16 +284,113 @@ def main():
                                f"CFL {prm['cfl']}, RK5 steps" if kind == "jet" else
                                f"periodic box {nx}^3, {args.precision}, CFL {prm['cfl']}",
                    "points": npts, "precision": args.precision,
-                   "dt_last": float(dts[-1])},
+                   "dt_last": r["dt_last"], "hbm_footprint_gb": r["hbm_gb"],
+                   "device_used_gb": r["device_used_gb"],
+                   "device_total_gb": r["device_total_gb"]},
         "roofline": roof,
     }
-    s.close()
+    if not args.no_extras:
+        other = "fp32" if args.precision == "fp64" else "fp64"
+        print(f"[bench] same workload in {other}", file=sys.stderr, flush=True)
+        r2 = time_rk(args.config, other, args.steps, args.warmup, dev)
+        v2 = npts * 5 * args.steps / r2["wall"] / 1e6
+        fp32_v, fp64_v = (v2, value) if other == "fp32" else (value, v2)
+        out["precision_forms"] = {"fp64": round(fp64_v, 2), "fp32": round(fp32_v, 2),
+                                  "fp32_over_fp64": round(fp32_v / fp64_v, 3),
+                                  "unit": "Mpoint-RK-stage updates/s"}
+        print("[bench] adjoint timing", file=sys.stderr, flush=True)
+        out["adjoint"] = time_adjoint("adj2M", dev)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.config)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def time_rk(config, precision, steps, warmup, dev):
+    """Wall time of `steps` RK5 steps (CFL dt) of a workload resident in HBM,
+    with the stage kernel's launches timed by HIP events on its stream."""
+    import torch
+    from paper_2301_00817_amd.solver import Solver
+    prm, xyz, fill, inflow = make_workload(config, dev)
+    s = Solver(prm, xyz, inflow, precision=precision, device=dev)
+    del xyz
+    torch.cuda.empty_cache()
+    nx, nr, nth = s.shape
+    Qn = s.field(5, dtype=torch.float64, fill=0.0)
+    fill(s.interior(Qn))
+    torch.cuda.synchronize()
+    hbm = torch.cuda.max_memory_allocated(dev) / 1e9
+    _, _, held = s.query()
+    print(f"[bench] device bytes held by the library {held / 1e9:.1f} GB, state "
+          f"{Qn.numel() * 8 / 1e9:.1f} GB, torch peak {hbm:.1f} GB", file=sys.stderr, flush=True)
+    print(f"[bench] {config} {nx}x{nr}x{nth} {precision}: warmup {warmup}",
+          file=sys.stderr, flush=True)
+    if warmup:
+        s.rk5_step(Qn, warmup)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {steps} steps", file=sys.stderr, flush=True)
+    s.profile(True)
+    s.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dts = s.rk5_step(Qn, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, kms = s.profile_read()
+    s.profile(False)
+    assert bool(torch.isfinite(s.interior(Qn)).all()), "state is not finite"
+    _, _, held = s.query()
+    free, total = torch.cuda.mem_get_info(dev)
+    r = {"shape": s.shape, "params": prm, "wall": wall, "launches": launches, "kernel_ms": kms,
+         "dt_last": float(dts[-1]), "hbm_gb": round((held + Qn.numel() * 8) / 1e9, 2),
+         "device_used_gb": round((total - free) / 1e9, 1), "device_total_gb": round(total / 1e9, 1)}
+    s.close()
+    del Qn
+    torch.cuda.empty_cache()
+    return r
+
+
+def time_adjoint(config, dev, reps=20):
+    """Mean time of les_residual_vjp and of les_residual (ghost fill
+    included in both) on one state, by HIP events on the call stream."""
+    import torch
+    from cases import flow, problems
+    from paper_2301_00817_amd.solver import Solver
+    prm, xyz, fill, inflow = make_workload(config, dev)
+    s = Solver(prm, xyz, inflow, precision="fp64", device=dev)
+    del xyz
+    Qp = s.field(5, dtype=torch.float64, fill=0.0)
+    fill(s.interior(Qp))
+    nx, nr, nth = s.shape
+    Rb = s.pad(problems.seeded_field((5, nth, nr, nx), 3, flow.FIELD_COTANGENT, device=dev),
+               fill=0.0)
+    Qb = s.field(5, dtype=torch.float64)
+    R = s.field(5)
+    ib = s.new_inflow_bar()
+    for _ in range(3):
+        s.residual(Qp, R)
+        s.residual_vjp(Qp, Rb, Qb, ib)
+    st = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    for _ in range(reps):
+        s.residual(Qp, R)
+    ev[1].record(st)
+    for _ in range(reps):
+        s.residual_vjp(Qp, Rb, Qb, ib)
+    ev[2].record(st)
+    torch.cuda.synchronize()
+    tr = ev[0].elapsed_time(ev[1]) / reps
+    tv = ev[1].elapsed_time(ev[2]) / reps
+    nx, nr, nth = s.shape
+    s.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"jet mesh {nx}x{nr}x{nth}, fp64, seeded Gaussian cotangent",
+            "vjp_per_s": round(1e3 / tv, 2), "vjp_ms": round(tv, 4),
+            "residual_ms": round(tr, 4), "vjp_over_residual": round(tv / tr, 3)}
 
 
 if __name__ == "__main__":

@@ -5,17 +5,18 @@
 // separately).  FP64, gather form: every output is accumulated by one
 // thread, with no floating-point atomics, so results are deterministic.
 //
-// Passes (scratch arrays in the padded layout):
-//   1. point quantities G^d, lambda_bar^d, nu^d of every point of [-1, n]^3
-//      (the two-pass reference point kernel);
-//   2. per point: cotangents of its point quantities and of its W from the
-//      (up to) four faces per direction whose stencil contains it;
-//   3. per point of [-1, n]^3: reverse of the point function -> cotangents
-//      of the state, of (u, v, w, T, p), of the central differences and of
-//      the neighbours' pressures;
-//   4. per padded point: gather the neighbours' contributions, reverse the
-//      primitive map -> cotangent of the padded state;
-//   5. transposes of the ghost fill in reverse order (zeta, eta, xi): ghost
+// Passes (36 scratch variables in the padded layout):
+//   1. primitives of every padded point; lambda_bar^d and nu^d of every
+//      point of [-1, n]^3; Rbar / J^-1 at the interior;
+//   2. per padded point: cotangents of its G^d, lambda_bar^d, nu^d and W
+//      from the (up to) four faces per direction whose stencil contains it,
+//      then (points of [-1, n]^3) the reverse of the point function; the
+//      part of the state cotangent that depends on the point alone is
+//      finished here, the cotangents of its central differences and sensor
+//      neighbour pressures are stored;
+//   3. per padded point: the neighbours' contributions through its
+//      primitives are added -> cotangent of the padded state;
+//   4. transposes of the ghost fill in reverse order (zeta, eta, xi): ghost
 //      cotangents go to the points they were computed from, through the
 //      exact Jacobians of the boundary states (dual numbers).
 #include "bc.hpp"
@@ -53,14 +54,126 @@ __device__ __forceinline__ void wvec_at(const double* Q, const Grid& g, int o,
 }  // namespace
 
 // scratch layout (variables of the padded layout)
-enum { A2_GB = 0, A2_LBB = 15, A2_NUB = 18, A2_WB = 21, A2_N = 26 };
-enum { A3_QD = 0, A3_PRB = 5, A3_DLB = 10, A3_NC = 22, A3_N = 25 };
-static_assert(21 + A2_N + A3_N == VJP_SCRATCH_VARS, "scratch size");
+enum {
+  S_PR = 0,    // (u, v, w, T, p) of every padded point
+  S_LB = 5,    // lambda_bar^d, points of [-1, n]^3
+  S_NU = 8,    // nu^d, points of [-1, n]^3
+  S_RT = 11,   // Rbar / J^-1 at interior points, 0 at the other padded points
+  S_PQ = 16,   // state cotangent of the point's own terms
+  S_DL = 21,   // cotangents of the central differences (d, u v w T), [-1, n]^3
+  S_NC = 33,   // cotangent of each sensor neighbour pressure (d), [-1, n]^3
+  S_N = 36
+};
+static_assert(S_N == VJP_SCRATCH_VARS, "scratch size");
 
-// Pass 2: face adjoints gathered at each padded point.
-__global__ __launch_bounds__(256) void k_adj_face(const double* __restrict__ Q, const double* __restrict__ M, Grid g,
-                           Phys<double> ph, const double* __restrict__ PT,
-                           const double* __restrict__ Rb, double* __restrict__ A2) {
+// Pass 1, one thread per padded point: its primitives and Rbar / J^-1
+// (zero off the interior); for points of [-1, n]^3 also lambda_bar^d and
+// nu^d (the face dissipation coefficients, as in the point function).
+__global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
+                                                  const double* __restrict__ M, Grid g,
+                                                  Phys<double> ph, const double* __restrict__ Rb,
+                                                  double* __restrict__ SC) {
+  const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG, NT = g.nth + 2 * NG;
+  const long long tot = (long long)NX * NR * NT;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= tot) return;
+  const int i = (int)(t % NX) - NG;
+  const int j = (int)((t / NX) % NR) - NG;
+  const int k = (int)(t / ((long long)NX * NR)) - NG;
+  const int o = g.at(i, j, k);
+  const int step[3] = {1, g.pitch, g.plane};
+  double q[5], pr[5];
+  load5d(Q, g, o, q);
+  prim5(q, ph, pr);
+  for (int c = 0; c < 5; ++c) SC[(long long)(S_PR + c) * g.vs + o] = pr[c];
+  const double iV = 1.0 / M[9LL * g.vs + o];
+  const bool inner = interior(g, i, j, k);
+  for (int c = 0; c < 5; ++c)   // zero off the interior: R has no entries there
+    SC[(long long)(S_RT + c) * g.vs + o] = inner ? Rb[(long long)c * g.vs + o] * iV : 0.0;
+  if (!in_r1(g, i, j, k)) return;
+  const double a = sqrt(pr[3]);
+  const double aiV = fabs(iV);
+  double lam[3];
+  for (int d = 0; d < 3; ++d) {
+    const double S0 = M[(long long)(3 * d) * g.vs + o], S1 = M[(long long)(3 * d + 1) * g.vs + o],
+                 S2 = M[(long long)(3 * d + 2) * g.vs + o];
+    const double Uc = S0 * pr[0] + S1 * pr[1] + S2 * pr[2];
+    lam[d] = (fabs(Uc) + a * sqrt(S0 * S0 + S1 * S1 + S2 * S2)) * aiV;
+    double qm[5], qp[5];
+    load5d(Q, g, o - step[d], qm);
+    load5d(Q, g, o + step[d], qp);
+    const double pm = pressure(qm, ph), pp = pressure(qp, ph);
+    const double num = pp - 2.0 * pr[4] + pm, den = pp + 2.0 * pr[4] + pm;
+    SC[(long long)(S_NU + d) * g.vs + o] = fabs(num) / den;
+  }
+  const double s01 = sqrt(lam[0] * lam[1]), s02 = sqrt(lam[0] * lam[2]),
+               s12 = sqrt(lam[1] * lam[2]);
+  SC[(long long)(S_LB + 0) * g.vs + o] = lam[0] + s01 + s02;
+  SC[(long long)(S_LB + 1) * g.vs + o] = lam[1] + s01 + s12;
+  SC[(long long)(S_LB + 2) * g.vs + o] = lam[2] + s02 + s12;
+}
+
+// Coefficients of one face L | L+1 along d: the flux cotangent
+// Fb = Rbar/J^-1 (L) - Rbar/J^-1 (L+1) (interior terms only) and, for a
+// face with dissipation, lambda_f, eps2, eps4, V_f.
+struct FaceCoef {
+  double Fb[5];
+  double lf, e2, e4, k4m, Vf;
+  bool nu_left;   // the eps2 max takes the left sensor
+  bool dis;       // the face carries dissipation
+};
+
+__device__ __forceinline__ void face_coef(const double* SC, const double* M, const Grid& g,
+                                          const Phys<double>& ph, int d, int L, int n, int oL,
+                                          int sd, FaceCoef& f) {
+  const int oR = oL + sd;
+  for (int c = 0; c < 5; ++c)      // S_RT is zero off the interior
+    f.Fb[c] = SC[(long long)(S_RT + c) * g.vs + oL] - SC[(long long)(S_RT + c) * g.vs + oR];
+  f.dis = !((L == -1 && ph.phys_face[d][0]) || (L == n - 1 && ph.phys_face[d][1]));
+  if (!f.dis) return;
+  const double nuL = SC[(long long)(S_NU + d) * g.vs + oL];
+  const double nuR = SC[(long long)(S_NU + d) * g.vs + oR];
+  f.lf = 0.5 * (SC[(long long)(S_LB + d) * g.vs + oL] + SC[(long long)(S_LB + d) * g.vs + oR]);
+  f.Vf = 0.5 * (M[9LL * g.vs + oL] + M[9LL * g.vs + oR]);
+  f.nu_left = nuL >= nuR;
+  f.e2 = ph.k2 * fmax(nuL, nuR);
+  f.k4m = ph.k4 - f.e2;
+  f.e4 = fmax(0.0, f.k4m);
+}
+
+// Reverse of the dissipation of a face at one of its two inner points:
+// adds the cotangent of that point's W (sign +1 for the right point, -1 for
+// the left), of its lambda_bar and (when the eps2 max took its sensor) of
+// its nu.  D = lf (e2 (W_R - W_L) - e4 (W_{R+1} - 3 W_R + 3 W_L - W_{L-1}))
+// enters the flux as -V_f D.
+__device__ __forceinline__ void face_self(const FaceCoef& f, const double* Wm, const double* WL,
+                                          const double* WR, const double* Wp, double sign,
+                                          bool takes_nu, const Phys<double>& ph, double wb[5],
+                                          double& lbb, double& nub) {
+  double lf_b = 0.0, e2_b = 0.0, e4_b = 0.0;
+  for (int c = 0; c < 5; ++c) {
+    const double Db = -f.Vf * f.Fb[c];
+    const double A = WR[c] - WL[c];
+    const double B = Wp[c] - 3.0 * WR[c] + 3.0 * WL[c] - Wm[c];
+    lf_b += Db * (f.e2 * A - f.e4 * B);
+    e2_b += Db * f.lf * A;
+    e4_b -= Db * f.lf * B;
+    wb[c] += sign * f.lf * (f.e2 + 3.0 * f.e4) * Db;
+  }
+  if (f.k4m > 0.0) e2_b -= e4_b;
+  lbb += 0.5 * lf_b;
+  if (takes_nu) nub += ph.k2 * e2_b;
+}
+
+// Pass 2, one thread per padded point p: the cotangents that the faces
+// whose stencils contain p send to its point quantities (G^d, lambda_bar^d,
+// nu^d) and to its W; then, for p in [-1, n]^3, the reverse of the point
+// function.  Writes the state cotangent of everything that depends on p
+// alone (S_PQ) and the cotangents of p's central differences and sensor
+// neighbour pressures (S_DL, S_NC), which pass 3 hands to the neighbours.
+__global__ __launch_bounds__(256) void k_adj_main(const double* __restrict__ Q,
+                                                  const double* __restrict__ M, Grid g,
+                                                  Phys<double> ph, double* __restrict__ SC) {
   const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG, NT = g.nth + 2 * NG;
   const long long tot = (long long)NX * NR * NT;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -70,109 +183,100 @@ __global__ __launch_bounds__(256) void k_adj_face(const double* __restrict__ Q, 
   const int nn[3] = {g.nx, g.nr, g.nth};
   const int step[3] = {1, g.pitch, g.plane};
   const int o = g.at(pos[0], pos[1], pos[2]);
-  double gb[3][5] = {}, lbb[3] = {}, nub[3] = {}, wb[5] = {};
+  const bool r1 = in_r1(g, pos[0], pos[1], pos[2]);
+  double gb[3][5], lbb[3] = {0, 0, 0}, nub[3] = {0, 0, 0}, wb[5] = {0, 0, 0, 0, 0};
+  for (int d = 0; d < 3; ++d)
+    for (int c = 0; c < 5; ++c) gb[d][c] = 0.0;
+
   for (int d = 0; d < 3; ++d) {
-    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
     if (pos[d1] < 0 || pos[d1] >= nn[d1] || pos[d2] < 0 || pos[d2] >= nn[d2]) continue;
-    const int s = pos[d];
-    for (int L = s - 2; L <= s + 1; ++L) {
-      if (L < -1 || L > nn[d] - 1) continue;
-      const int oL = o + (L - s) * step[d];
-      const int oR = oL + step[d];
-      double Fb[5];
-      for (int c = 0; c < 5; ++c) {
-        const double a = L >= 0 ? Rb[(long long)c * g.vs + oL] / M[9LL * g.vs + oL] : 0.0;
-        const double b = L + 1 <= nn[d] - 1 ? Rb[(long long)c * g.vs + oR] / M[9LL * g.vs + oR] : 0.0;
-        Fb[c] = a - b;
+    const int s = pos[d], sd = step[d], n = nn[d];
+    // faces L = s-2 and s+1: p is the outer point of their 4-point stencil
+    if (s - 2 >= -1) {
+      FaceCoef f;
+      face_coef(SC, M, g, ph, d, s - 2, n, o - 2 * sd, sd, f);
+      if (f.dis)
+        for (int c = 0; c < 5; ++c) wb[c] += f.lf * f.e4 * f.Vf * f.Fb[c];
+    }
+    if (s + 1 <= n - 1) {
+      FaceCoef f;
+      face_coef(SC, M, g, ph, d, s + 1, n, o + sd, sd, f);
+      if (f.dis)
+        for (int c = 0; c < 5; ++c) wb[c] -= f.lf * f.e4 * f.Vf * f.Fb[c];
+    }
+    // faces L = s-1 (p is its right point) and L = s (p is its left point)
+    FaceCoef fb, fc;
+    const bool hb = s - 1 >= -1, hc = s <= n - 1;
+    if (hb) face_coef(SC, M, g, ph, d, s - 1, n, o - sd, sd, fb);
+    if (hc) face_coef(SC, M, g, ph, d, s, n, o, sd, fc);
+    for (int c = 0; c < 5; ++c)
+      gb[d][c] = 0.5 * ((hb ? fb.Fb[c] : 0.0) + (hc ? fc.Fb[c] : 0.0));
+    const bool db = hb && fb.dis, dc = hc && fc.dis;
+    if (db || dc) {
+      // W on the line p-2 .. p+2; points outside the padded box (s = -1 or
+      // n) belong to no dissipative face stencil and are never used
+      double W[5][5];
+      for (int m = 0; m < 5; ++m) {
+        const int pt = min(max(s + m - 2, -NG), n - 1 + NG);   // clamped: unused then
+        const int om = o + (pt - s) * sd;
+        load5d(Q, g, om, W[m]);
+        W[m][4] += SC[(long long)(S_PR + 4) * g.vs + om];
       }
-      const int role = s - L;   // -1: L-1, 0: L, 1: R, 2: R+1
-      if (role == 0 || role == 1)
-        for (int c = 0; c < 5; ++c) gb[d][c] += 0.5 * Fb[c];
-      const bool physical = (L == -1 && ph.phys_face[d][0]) || (L == nn[d] - 1 && ph.phys_face[d][1]);
-      if (physical) continue;
-      double Wm[5], WL[5], WR[5], Wp[5];
-      wvec_at(Q, g, oL - step[d], ph, Wm);
-      wvec_at(Q, g, oL, ph, WL);
-      wvec_at(Q, g, oR, ph, WR);
-      wvec_at(Q, g, oR + step[d], ph, Wp);
-      double GbL[5] = {}, GbR[5] = {}, Wbm[5] = {}, WbL[5] = {}, WbR[5] = {}, Wbp[5] = {};
-      double lbbL = 0, lbbR = 0, nubL = 0, nubR = 0;
-      face_flux_vjp(PT[(long long)(15 + d) * g.vs + oL], PT[(long long)(15 + d) * g.vs + oR],
-                    PT[(long long)(18 + d) * g.vs + oL], PT[(long long)(18 + d) * g.vs + oR],
-                    M[9LL * g.vs + oL], M[9LL * g.vs + oR], Wm, WL, WR, Wp, false, ph, Fb, GbL,
-                    GbR, lbbL, lbbR, nubL, nubR, Wbm, WbL, WbR, Wbp);
-      const double* wsel = role == -1 ? Wbm : role == 0 ? WbL : role == 1 ? WbR : Wbp;
-      for (int c = 0; c < 5; ++c) wb[c] += wsel[c];
-      if (role == 0) { lbb[d] += lbbL; nub[d] += nubL; }
-      if (role == 1) { lbb[d] += lbbR; nub[d] += nubR; }
+      if (db) face_self(fb, W[0], W[1], W[2], W[3], 1.0, !fb.nu_left, ph, wb, lbb[d], nub[d]);
+      if (dc) face_self(fc, W[1], W[2], W[3], W[4], -1.0, fc.nu_left, ph, wb, lbb[d], nub[d]);
     }
   }
-  for (int d = 0; d < 3; ++d) {
-    for (int c = 0; c < 5; ++c) A2[(long long)(A2_GB + 5 * d + c) * g.vs + o] = gb[d][c];
-    A2[(long long)(A2_LBB + d) * g.vs + o] = lbb[d];
-    A2[(long long)(A2_NUB + d) * g.vs + o] = nub[d];
+
+  double q[5];
+  load5d(Q, g, o, q);
+  double qb[5], prb[5] = {0, 0, 0, 0, 0};
+  for (int c = 0; c < 5; ++c) qb[c] = wb[c];
+  prb[4] = wb[4];                                  // W5 = E + p
+  if (r1) {
+    PointIn<double> in;
+    for (int c = 0; c < 5; ++c) {
+      in.q[c] = q[c];
+      in.pr[c] = SC[(long long)(S_PR + c) * g.vs + o];
+    }
+    double pm[3], pp[3];
+    for (int d = 0; d < 3; ++d) {
+      double m[5], pl[5];
+      load5d(SC + (long long)S_PR * g.vs, g, o - step[d], m);
+      load5d(SC + (long long)S_PR * g.vs, g, o + step[d], pl);
+      for (int f = 0; f < 4; ++f) in.dl[d][f] = 0.5 * (pl[f] - m[f]);
+      in.nu[d] = 0.0;                        // not used by the reverse
+      pm[d] = m[4];
+      pp[d] = pl[4];
+      for (int c = 0; c < 3; ++c) in.S[d][c] = M[(long long)(3 * d + c) * g.vs + o];
+    }
+    in.V = M[9LL * g.vs + o];
+    PointBar<double> bar = {};
+    point_quantities_vjp(in, ph, gb, lbb, bar);
+    for (int d = 0; d < 3; ++d) {
+      double side, centre;
+      sensor_vjp(pm[d], in.pr[4], pp[d], nub[d], side, centre);
+      bar.pr[4] += centre;
+      SC[(long long)(S_NC + d) * g.vs + o] = side;
+      for (int f = 0; f < 4; ++f) SC[(long long)(S_DL + 4 * d + f) * g.vs + o] = bar.dl[d][f];
+    }
+    for (int c = 0; c < 5; ++c) {
+      qb[c] += bar.q[c];
+      prb[c] += bar.pr[c];
+    }
   }
-  for (int c = 0; c < 5; ++c) A2[(long long)(A2_WB + c) * g.vs + o] = wb[c];
+  prim5_vjp(q, ph, prb, qb);
+  for (int c = 0; c < 5; ++c) SC[(long long)(S_PQ + c) * g.vs + o] = qb[c];
 }
 
-// Pass 3: reverse of the point function at the points of [-1, n]^3.
-__global__ __launch_bounds__(256) void k_adj_point(const double* __restrict__ Q, const double* __restrict__ M, Grid g,
-                            Phys<double> ph, const double* __restrict__ A2,
-                            double* __restrict__ A3) {
-  const int NX1 = g.nx + 2, NR1 = g.nr + 2, NT1 = g.nth + 2;
-  const long long tot = (long long)NX1 * NR1 * NT1;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= tot) return;
-  const int i = (int)(t % NX1) - 1;
-  const int j = (int)((t / NX1) % NR1) - 1;
-  const int k = (int)(t / ((long long)NX1 * NR1)) - 1;
-  const int o = g.at(i, j, k);
-  const int step[3] = {1, g.pitch, g.plane};
-  PointIn<double> in;
-  load5d(Q, g, o, in.q);
-  prim5(in.q, ph, in.pr);
-  double pm[3], pp[3];
-  for (int d = 0; d < 3; ++d) {
-    double q[5], m[5], pl[5];
-    load5d(Q, g, o - step[d], q);
-    prim5(q, ph, m);
-    load5d(Q, g, o + step[d], q);
-    prim5(q, ph, pl);
-    neighbour_terms(m, pl, in.pr[4], in.dl[d], in.nu[d]);
-    pm[d] = m[4];
-    pp[d] = pl[4];
-    for (int c = 0; c < 3; ++c) in.S[d][c] = M[(long long)(3 * d + c) * g.vs + o];
-  }
-  in.V = M[9LL * g.vs + o];
-  double Gb[3][5], lbb[3];
-  for (int d = 0; d < 3; ++d) {
-    for (int c = 0; c < 5; ++c) Gb[d][c] = A2[(long long)(A2_GB + 5 * d + c) * g.vs + o];
-    lbb[d] = A2[(long long)(A2_LBB + d) * g.vs + o];
-  }
-  PointBar<double> bar = {};
-  point_quantities_vjp(in, ph, Gb, lbb, bar);
-  double nc[3];
-  for (int d = 0; d < 3; ++d) {
-    double side, centre;
-    sensor_vjp(pm[d], in.pr[4], pp[d], A2[(long long)(A2_NUB + d) * g.vs + o], side, centre);
-    bar.pr[4] += centre;
-    nc[d] = side;
-  }
-  for (int c = 0; c < 5; ++c) {
-    A3[(long long)(A3_QD + c) * g.vs + o] = bar.q[c];
-    A3[(long long)(A3_PRB + c) * g.vs + o] = bar.pr[c];
-  }
-  for (int d = 0; d < 3; ++d) {
-    for (int f = 0; f < 4; ++f) A3[(long long)(A3_DLB + 4 * d + f) * g.vs + o] = bar.dl[d][f];
-    A3[(long long)(A3_NC + d) * g.vs + o] = nc[d];
-  }
-}
-
-// Pass 4: cotangent of the padded state; one thread per element of a
-// variable, so the pitch padding beyond the padded box is written (zero) too.
-__global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ Q, Grid g, Phys<double> ph,
-                             const double* __restrict__ A2, const double* __restrict__ A3,
-                             double* __restrict__ Qb) {
+// Pass 3: cotangent of the padded state = own part + the neighbours'
+// central-difference and sensor contributions through this point's
+// primitives.  One thread per element of a variable, so the pitch padding
+// beyond the padded box is written (zero) too.
+__global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ Q, Grid g,
+                                                    Phys<double> ph,
+                                                    const double* __restrict__ SC,
+                                                    double* __restrict__ Qb) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= g.vs) return;
   const int pos[3] = {o % g.pitch - NG, (o % g.plane) / g.pitch - NG, o / g.plane - NG};
@@ -181,29 +285,28 @@ __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ Q
     return;
   }
   const int step[3] = {1, g.pitch, g.plane};
-  double qb[5], prb[5] = {0, 0, 0, 0, 0};
-  for (int c = 0; c < 5; ++c) qb[c] = A2[(long long)(A2_WB + c) * g.vs + o];
-  prb[4] += qb[4];                               // W5 = E + p
-  if (in_r1(g, pos[0], pos[1], pos[2]))
-    for (int c = 0; c < 5; ++c) {
-      qb[c] += A3[(long long)(A3_QD + c) * g.vs + o];
-      prb[c] += A3[(long long)(A3_PRB + c) * g.vs + o];
-    }
+  double prb[5] = {0, 0, 0, 0, 0};
+  bool any = false;
   for (int d = 0; d < 3; ++d) {
     for (int sgn = -1; sgn <= 1; sgn += 2) {
       int p2[3] = {pos[0], pos[1], pos[2]};
       p2[d] += sgn;
       if (!in_r1(g, p2[0], p2[1], p2[2])) continue;
+      any = true;
       const int om = o + sgn * step[d];
       // this point is the +1 neighbour of om when sgn = -1, the -1 when sgn = +1
       const double h = sgn < 0 ? 0.5 : -0.5;
-      for (int f = 0; f < 4; ++f) prb[f] += h * A3[(long long)(A3_DLB + 4 * d + f) * g.vs + om];
-      prb[4] += A3[(long long)(A3_NC + d) * g.vs + om];
+      for (int f = 0; f < 4; ++f) prb[f] += h * SC[(long long)(S_DL + 4 * d + f) * g.vs + om];
+      prb[4] += SC[(long long)(S_NC + d) * g.vs + om];
     }
   }
-  double q[5];
-  load5d(Q, g, o, q);
-  prim5_vjp(q, ph, prb, qb);
+  double qb[5];
+  for (int c = 0; c < 5; ++c) qb[c] = SC[(long long)(S_PQ + c) * g.vs + o];
+  if (any) {
+    double q[5];
+    load5d(Q, g, o, q);
+    prim5_vjp(q, ph, prb, qb);
+  }
   for (int c = 0; c < 5; ++c) Qb[(long long)c * g.vs + o] = qb[c];
 }
 
@@ -373,18 +476,12 @@ hipError_t launch_accumulate(const double* x, double* y, long long n, hipStream_
 
 hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
                                const Phys<double>& ph, const int bc[6], const double ref_prim[5],
-                               double p_exit, const double* inflow, const double* Rb, double* PT,
-                               double* A2, double* A3, double* Qb, double* inflow_bar,
-                               hipStream_t s) {
-  hipError_t e = launch_residual_ref<double>(Q, M, g, ph, PT, nullptr, s);   // pass 1
-  if (e != hipSuccess) return e;
+                               double p_exit, const double* inflow, const double* Rb, double* SC,
+                               double* Qb, double* inflow_bar, hipStream_t s) {
   const long long npad = (long long)(g.nx + 2 * NG) * (g.nr + 2 * NG) * (g.nth + 2 * NG);
-  const long long nr1 = (long long)(g.nx + 2) * (g.nr + 2) * (g.nth + 2);
-  hipLaunchKernelGGL(k_adj_face, dim3(blocks_for(npad, 256)), dim3(256), 0, s, Q, M, g, ph, PT, Rb,
-                     A2);
-  hipLaunchKernelGGL(k_adj_point, dim3(blocks_for(nr1, 256)), dim3(256), 0, s, Q, M, g, ph, A2, A3);
-  hipLaunchKernelGGL(k_adj_gather, dim3(blocks_for(g.vs, 256)), dim3(256), 0, s, Q, g, ph, A2, A3,
-                     Qb);
+  hipLaunchKernelGGL(k_adj_prep, dim3(blocks_for(npad, 256)), dim3(256), 0, s, Q, M, g, ph, Rb, SC);
+  hipLaunchKernelGGL(k_adj_main, dim3(blocks_for(npad, 256)), dim3(256), 0, s, Q, M, g, ph, SC);
+  hipLaunchKernelGGL(k_adj_gather, dim3(blocks_for(g.vs, 256)), dim3(256), 0, s, Q, g, ph, SC, Qb);
   const double gamma = ph.gamma;
   hipLaunchKernelGGL(k_adjT_zeta, dim3(blocks_for((long long)(g.nx + 2 * NG) * (g.nr + 2 * NG), 256)),
                      dim3(256), 0, s, Qb, g);

@@ -499,10 +499,9 @@ static int residual_vjp_into(les_ctx* c, double* Q, const double* Rb, double* Qb
   if (r != LES_OK) return r;
   hipError_t e = ghosts<double>(c, Q, s);
   if (e == hipSuccess) {
-    const long long v = c->g.vs;
     e = launch_residual_vjp(Q, (const double*)c->M, c->g, c->ph64, c->p.bc, c->p.ref_prim,
-                            c->p.p_exit, c->inflow, Rb, c->adj, c->adj + 21 * v, c->adj + 47 * v,
-                            Qb, c->p.bc[0] == LES_BC_INFLOW ? inflow_bar : nullptr, s);
+                            c->p.p_exit, c->inflow, Rb, c->adj, Qb,
+                            c->p.bc[0] == LES_BC_INFLOW ? inflow_bar : nullptr, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "residual adjoint kernels");
   return LES_OK;

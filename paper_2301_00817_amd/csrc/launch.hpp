@@ -52,13 +52,12 @@ hipError_t launch_diagnostics(const double* Q, const TM* M, const Grid& g, const
 
 // Residual adjoint (FP64): Qb = (dR/dQ)^T Rb on the padded layout (ghost
 // entries zero); inflow_bar (5, nth, nr) accumulated when non-null.  Scratch
-// PT (21 variables), A2 (26), A3 (25); Q's ghosts must be filled.
+// SC of VJP_SCRATCH_VARS padded variables; Q's ghosts must be filled.
+constexpr int VJP_SCRATCH_VARS = 36;
 hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
                                const Phys<double>& ph, const int bc[6], const double ref_prim[5],
-                               double p_exit, const double* inflow, const double* Rb, double* PT,
-                               double* A2, double* A3, double* Qb, double* inflow_bar,
-                               hipStream_t s);
-constexpr int VJP_SCRATCH_VARS = 21 + 26 + 25;
+                               double p_exit, const double* inflow, const double* Rb, double* SC,
+                               double* Qb, double* inflow_bar, hipStream_t s);
 hipError_t launch_scale(const double* x, double a, double* y, long long n, hipStream_t s);
 hipError_t launch_interior_copy(const double* x, double* y, const Grid& g, hipStream_t s);
 hipError_t launch_accumulate(const double* x, double* y, long long n, hipStream_t s);

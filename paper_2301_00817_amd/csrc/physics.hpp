@@ -222,6 +222,7 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
   const T rho = in.q[0], u = in.pr[0], v = in.pr[1], w = in.pr[2], Tt = in.pr[3], p = in.pr[4];
   const T vel[3] = {u, v, w};
   const T a = tsqrt(Tt);
+  const T ia = T(1) / a;                       // 1/T = ia^2
   const T iV = trcp(in.V);
   const T aiV = tabs(iV);
   T Uc[3], Uc_b[3] = {0, 0, 0};
@@ -242,9 +243,10 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
     // lb0 = l0 + s01 + s02, lb1 = l1 + s01 + s12, lb2 = l2 + s02 + s12
     const T s01_b = lbb[0] + lbb[1], s02_b = lbb[0] + lbb[2], s12_b = lbb[1] + lbb[2];
     T lam_b[3] = {lbb[0], lbb[1], lbb[2]};
-    if (s01 > T(0)) { lam_b[0] += s01_b * lam[1] / (T(2) * s01); lam_b[1] += s01_b * lam[0] / (T(2) * s01); }
-    if (s02 > T(0)) { lam_b[0] += s02_b * lam[2] / (T(2) * s02); lam_b[2] += s02_b * lam[0] / (T(2) * s02); }
-    if (s12 > T(0)) { lam_b[1] += s12_b * lam[2] / (T(2) * s12); lam_b[2] += s12_b * lam[1] / (T(2) * s12); }
+    // d sqrt(x y)/dx = y / (2 sqrt(x y))
+    if (s01 > T(0)) { const T h = s01_b / (T(2) * s01); lam_b[0] += h * lam[1]; lam_b[1] += h * lam[0]; }
+    if (s02 > T(0)) { const T h = s02_b / (T(2) * s02); lam_b[0] += h * lam[2]; lam_b[2] += h * lam[0]; }
+    if (s12 > T(0)) { const T h = s12_b / (T(2) * s12); lam_b[1] += h * lam[2]; lam_b[2] += h * lam[1]; }
     for (int d = 0; d < 3; ++d) {
       Uc_b[d] += lam_b[d] * aiV * (Uc[d] < T(0) ? T(-1) : T(1));
       a_b += lam_b[d] * Sn[d] * aiV;
@@ -257,7 +259,8 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
     for (int f = 0; f < 4; ++f)
       for (int m = 0; m < 3; ++m)
         g[f][m] = (in.S[0][m] * dl[0][f] + in.S[1][m] * dl[1][f] + in.S[2][m] * dl[2][f]) * iV;
-    const T mu = Tt * a * ph.suth1 / (Tt + ph.suth);
+    const T iTS = T(1) / (Tt + ph.suth);
+    const T mu = Tt * a * ph.suth1 * iTS;
     T mut = 0, Smag = 0, Csd2 = 0, sij[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) sij[i][j] = T(0.5) * (g[i][j] + g[j][i]);
@@ -313,12 +316,14 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
       // mut = rho Csd2 Smag, Smag = sqrt(2 sum sij^2): dSmag/dg_ij = 2 sij / Smag
       rho_b += mut_b * Csd2 * Smag;
       const T Smag_b = mut_b * rho * Csd2;
-      if (Smag > T(0))
+      if (Smag > T(0)) {
+        const T h = Smag_b * T(2) / Smag;
         for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) g_b[i][j] += Smag_b * T(2) * sij[i][j] / Smag;
+          for (int j = 0; j < 3; ++j) g_b[i][j] += h * sij[i][j];
+      }
     }
     // Sutherland: dmu/dT = mu (3/(2T) - 1/(T + S))
-    Tt_b += mu_b * mu * (T(1.5) / Tt - T(1) / (Tt + ph.suth));
+    Tt_b += mu_b * mu * (T(1.5) * ia * ia - iTS);
     // g[f][m] = iV sum_d S[d][m] dl[d][f]
     for (int d = 0; d < 3; ++d)
       for (int f = 0; f < 4; ++f) {
@@ -343,7 +348,7 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
   }
   for (int d = 0; d < 3; ++d)
     for (int i = 0; i < 3; ++i) vel_b[i] += Uc_b[d] * in.S[d][i];
-  Tt_b += a_b / (T(2) * a);
+  Tt_b += T(0.5) * a_b * ia;
   bar.q[0] += rho_b;
   bar.pr[0] += vel_b[0];
   bar.pr[1] += vel_b[1];
@@ -382,11 +387,11 @@ __host__ __device__ inline void prim5_vjp(const T q[5], const Phys<T>& ph, const
 template <typename T>
 __host__ __device__ inline void sensor_vjp(T pm, T p0, T pp, T nb, T& side, T& centre) {
   const T num = pp - T(2) * p0 + pm;
-  const T den = pp + T(2) * p0 + pm;
-  const T nu = tabs(num) / den;
+  const T iden = T(1) / (pp + T(2) * p0 + pm);
+  const T nu = tabs(num) * iden;
   const T sg = num < T(0) ? T(-1) : T(1);
-  side = nb * (sg - nu) / den;
-  centre = nb * T(-2) * (sg + nu) / den;
+  side = nb * (sg - nu) * iden;
+  centre = nb * T(-2) * (sg + nu) * iden;
 }
 
 // Reverse of face_flux: accumulate the cotangents of G_L, G_R, lambda_bar_L/R,

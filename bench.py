@@ -50,9 +50,14 @@ STAGE_BYTES = {"fp64": (5 + 10 + 5 + 5) * 8, "fp32": (5 + 10 + 5) * 4 + 5 * 8 + 
 DOMINANT_KERNEL = "k_fused"
 
 
+# the sources the stage kernel is compiled from (its traffic record is tied
+# to them)
+STAGE_SOURCES = ("common.hpp", "physics.hpp", "residual_fused.hip")
+
+
 def source_hash():
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in STAGE_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -221,6 +226,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other-precision run and the adjoint timing")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only time les_residual_vjp against les_residual (160x100x128 jet)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only time a device copy of this many GiB (counter calibration)")
     ap.add_argument("--rocprof-summary", nargs=3, metavar=("CSV_DIR", "OUT", "COMMAND"),
@@ -249,6 +256,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_probe:
         copy_probe(args.copy_probe, dev)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": time_adjoint("adj2M", dev)}), flush=True)
         return
     from cases import problems
     kind = problems.CONFIGS[args.config]["kind"]

@@ -21,7 +21,7 @@
 //      exact Jacobians of the boundary states (dual numbers).
 #include "bc.hpp"
 #include "launch.hpp"
-#include "physics.hpp"
+#include "physics_vjp.hpp"
 
 namespace lesjet {
 

@@ -1,9 +1,9 @@
 // Fused residual / Runge-Kutta stage kernel (section "Spatial
 // Discretization" with the stage update of eq. localdt as an epilogue).
 //
-// Work decomposition (2.5-D): a block of 64 x 8 threads owns a ring-1 tile
-// of (i, j) columns and marches along k over a chunk of planes.  For each
-// plane kk it
+// Work decomposition (2.5-D): a block of Tile<T>::X x Tile<T>::Y threads
+// owns a ring-1 tile of (i, j) columns and marches along k over a chunk of
+// planes.  For each plane kk it
 //   (a) writes the state and primitives of the plane (ring-2 tile, two-point
 //       halo for the fourth differences) to LDS,
 //   (b) computes the point quantities G^d, lambda_bar^d, nu^d of every

@@ -8,7 +8,7 @@
 #include <random>
 
 #include "bc.hpp"
-#include "physics.hpp"
+#include "physics_vjp.hpp"
 
 using namespace lesjet;
 

@@ -88,7 +88,8 @@ def make_workload(name, device, chunk_points=64 * 2 ** 20):
             Qi[:, k0:k1] = flow.jet_state(X, R, TH, seed=cfg["seed"], k0=k0, k1=k1, device=device)
 
     inflow = flow.jet_inflow(R, TH, seed=cfg["seed"], device=device)
-    return problems.jet_params(), xyz, fill, inflow
+    prm = problems.jet_params() if cfg.get("sgs", True) else problems.jet_params(sgs_model=0)
+    return prm, xyz, fill, inflow
 
 
 def cpu_baseline(name):
@@ -291,7 +292,9 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32-storage/f64-accumulate",
         "data": "synthetic",
         "config": {"workload": f"jet mesh {nx}x{nr}x{nth} ({npts} points), {args.precision}, "
-                               f"CFL {prm['cfl']}, RK5 steps" if kind == "jet" else
+                               f"CFL {prm['cfl']}, RK5 steps"
+                               + ("" if prm.get("sgs_model", 1) else ", no SGS model")
+                               if kind == "jet" else
                                f"periodic box {nx}^3, {args.precision}, CFL {prm['cfl']}",
                    "points": npts, "precision": args.precision,
                    "dt_last": r["dt_last"], "hbm_footprint_gb": r["hbm_gb"],

@@ -98,3 +98,13 @@ CONFIGS = {
     "adj2M": dict(kind="jet", shape=(160, 100, 128), steps=20, seed=4),
     "big1B": dict(kind="jet", shape=(1250, 640, 1250), steps=20, seed=2),
 }
+
+# The paper's mesh family A-I (axial x radial x azimuthal; its 361 azimuthal
+# points repeat the periodic point, so 360 distinct ones here), run as the
+# paper ran them: no subgrid model.
+PAPER_MESHES = {
+    "A": (128, 128), "B": (256, 128), "C": (256, 256), "D": (512, 256), "E": (512, 512),
+    "F": (1024, 512), "G": (1024, 1024), "H": (2048, 1024), "I": (1700, 1700),
+}
+for _m, (_nx, _nr) in PAPER_MESHES.items():
+    CONFIGS["mesh" + _m] = dict(kind="jet", shape=(_nx, _nr, 360), steps=10, seed=2, sgs=False)

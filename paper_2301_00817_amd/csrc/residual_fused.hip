@@ -33,8 +33,20 @@ namespace lesjet {
 // blocks per CU); both measured fastest among 64x8, 32x8 and 16x16 on the
 // jet meshes.
 template <typename T> struct Tile;
+#if defined(LESJET_TILE64_X) && defined(LESJET_TILE64_Y) && defined(LESJET_TILE64_PER_CU)
+template <> struct Tile<double> {
+  static constexpr int X = LESJET_TILE64_X, Y = LESJET_TILE64_Y, PER_CU = LESJET_TILE64_PER_CU;
+};
+#else
 template <> struct Tile<double> { static constexpr int X = 16, Y = 16, PER_CU = 2; };
+#endif
+#if defined(LESJET_TILE32_X) && defined(LESJET_TILE32_Y) && defined(LESJET_TILE32_PER_CU)
+template <> struct Tile<float> {
+  static constexpr int X = LESJET_TILE32_X, Y = LESJET_TILE32_Y, PER_CU = LESJET_TILE32_PER_CU;
+};
+#else
 template <> struct Tile<float> { static constexpr int X = 32, Y = 8, PER_CU = 3; };
+#endif
 
 constexpr int NPQ = 8;                // G(5), lambda_bar, nu, V per direction
 

@@ -43,7 +43,7 @@ def _gpu_J_and_grad(s, pb, grid, seed, dt, nsteps, every, fn, coef0=None):
     Q0, inflow = _inputs(grid, seed, coef, "cuda")
     _, J = A.rollout(s, A.pad_state(s, Q0), inflow, dt, nsteps, every=every, functional=fn)
     (g,) = torch.autograd.grad(J, coef)
-    return float(J), g.cpu().numpy()
+    return float(J.detach()), g.cpu().numpy()
 
 
 def _gpu_J(s, grid, seed, dt, nsteps, fn, coef):

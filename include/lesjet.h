@@ -5,7 +5,7 @@
  *
  * Method: Junqueira-Junior, Azevedo, Yamouni, Wolf, arXiv 2301.00817,
  * sections "Large Eddy Simulation Filtering", "Subgrid Scale Modeling"
- * (static Smagorinsky), "Transformation of Coordinates", "Numerical
+ * (static Smagorinsky and Vreman models), "Transformation of Coordinates", "Numerical
  * Formulation" (centred fluxes, Turkel-Vatsa artificial dissipation, Jameson
  * 5-stage RK) and "Boundary Conditions".
  *
@@ -77,7 +77,14 @@ enum les_bc {
   LES_BC_FARFIELD = 4     /* eta+: Riemann invariants with ref_prim */
 };
 
-enum les_sgs { LES_SGS_NONE = 0, LES_SGS_SMAGORINSKY = 1 };
+/* Subgrid-scale eddy viscosity (subsection "Subgrid Scale Modeling"), in
+ * jet-viscosity units (divided by visc_coef), filter width |J^-1|^(1/3):
+ *   SMAGORINSKY  mu_sgs = rho (Cs Delta)^2 sqrt(2 S_ij S_ij);
+ *   VREMAN       mu_sgs = rho c sqrt(B_beta / (alpha_ij alpha_ij)), c = 2.5 Cs^2,
+ *                alpha_ij = d u_j / d x_i, beta_ij = Delta^2 alpha_mi alpha_mj,
+ *                B_beta = b11 b22 - b12^2 + b11 b33 - b13^2 + b22 b33 - b23^2,
+ *                zero where alpha_ij alpha_ij = 0 (or B_beta <= 0 by rounding). */
+enum les_sgs { LES_SGS_NONE = 0, LES_SGS_SMAGORINSKY = 1, LES_SGS_VREMAN = 2 };
 
 typedef struct les_params {
   int32_t nx, nr, nth;        /* interior points along xi, eta, zeta (each >= 5) */
@@ -88,7 +95,7 @@ typedef struct les_params {
   double Pr, Pr_sgs;          /* molecular and SGS Prandtl numbers */
   double visc_coef;           /* M/Re factor of the viscous fluxes (0: inviscid) */
   double suth_S;              /* Sutherland constant over the reference temperature */
-  double Cs;                  /* Smagorinsky constant */
+  double Cs;                  /* Smagorinsky constant (Vreman: c = 2.5 Cs^2) */
   double k2, k4;              /* dissipation constants */
   double cfl;                 /* CFL number for the global time step */
   double rk_alpha[5];         /* stage coefficients alpha_1..alpha_5 */

@@ -269,6 +269,17 @@ class Brute:
                     s2 += (0.5 * (g[i][j] + g[j][i])) ** 2
             delta = abs(V) ** (1.0 / 3.0)
             mut = P["rho"] * (prm["Cs"] * delta) ** 2 * math.sqrt(2.0 * s2) / Cv
+        elif prm["sgs_model"] == 2 and prm["Cs"] != 0.0:
+            # Vreman: alpha_ij = d u_j / d x_i, beta_ij = Delta^2 alpha_mi alpha_mj
+            alpha = [[g[j][i] for j in range(3)] for i in range(3)]
+            delta = abs(V) ** (1.0 / 3.0)
+            beta = [[delta ** 2 * sum(alpha[m][i] * alpha[m][j] for m in range(3))
+                     for j in range(3)] for i in range(3)]
+            B = (beta[0][0] * beta[1][1] - beta[0][1] ** 2 + beta[0][0] * beta[2][2]
+                 - beta[0][2] ** 2 + beta[1][1] * beta[2][2] - beta[1][2] ** 2)
+            aa = sum(alpha[i][j] ** 2 for i in range(3) for j in range(3))
+            c = 2.5 * prm["Cs"] ** 2
+            mut = P["rho"] * c * math.sqrt(B / aa) / Cv if aa > 0.0 and B > 0.0 else 0.0
         div = g[0][0] + g[1][1] + g[2][2]
         tau = [[(mu + mut) * (g[i][j] + g[j][i] - (2.0 / 3.0 if i == j else 0.0) * div)
                 for j in range(3)] for i in range(3)]

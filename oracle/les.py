@@ -35,7 +35,9 @@ also listed in the design notes):
   R5  the eta metric row is the cofactor grad eta = J (r_zeta x r_xi).
   R6  heat flux q = -(kappa + kappa_sgs) grad T (down-gradient).
   R7  Smagorinsky mu_sgs = rho (Cs Delta)^2 |S|; in units of the jet
-      viscosity it is divided by visc_coef = M/Re.
+      viscosity it is divided by visc_coef = M/Re.  The Vreman variant
+      (sgs_model 2) uses the same width Delta in every direction and the
+      same units: mu_sgs = rho c sqrt(B_beta / alpha_ij alpha_ij) / visc_coef.
   R9  filter width Delta = |V|^(1/3).
   R10 Sutherland mu = T^1.5 (1 + S)/(T + S), S = 110.4 K / 288.15 K.
   R11 viscous face flux = average of the two point viscous fluxes, with point
@@ -423,6 +425,19 @@ def point_terms(Qp, geo, prm):
             Smag = np.sqrt(2.0 * Sij2)
             delta_f = rabs(V) ** (1.0 / 3.0)                # filter width (R9)
             mu_t = rho1 * (prm["Cs"] * delta_f) ** 2 * Smag / Cv   # (R7)
+        elif prm["sgs_model"] == 2 and prm["Cs"] != 0.0:
+            # Vreman model (subsection "Vreman Model"): alpha_ij = d u_j/d x_i,
+            # beta_ij = Delta^2 alpha_mi alpha_mj, c = 2.5 Cs^2, mu_t = 0 where
+            # alpha_ij alpha_ij = 0 (and where rounding makes B_beta <= 0)
+            delta_f = rabs(V) ** (1.0 / 3.0)
+            beta = [[delta_f ** 2 * (gu[i][0] * gu[j][0] + gu[i][1] * gu[j][1] + gu[i][2] * gu[j][2])
+                     for j in range(3)] for i in range(3)]
+            B = (beta[0][0] * beta[1][1] - beta[0][1] ** 2 + beta[0][0] * beta[2][2]
+                 - beta[0][2] ** 2 + beta[1][1] * beta[2][2] - beta[1][2] ** 2)
+            aa = sum(gu[i][j] ** 2 for i in range(3) for j in range(3))
+            ok = (np.real(aa) > 0.0) & (np.real(B) > 0.0)
+            ratio = np.sqrt(np.where(ok, B, 1.0) / np.where(ok, aa, 1.0))
+            mu_t = np.where(ok, rho1 * (2.5 * prm["Cs"] ** 2) * ratio / Cv, 0.0 * rho1)
         else:
             mu_t = np.zeros_like(mu)
         out["mu_t"] = mu_t

@@ -119,9 +119,10 @@ static int validate(const les_params* p, std::string& why) {
     if (!(p->ref_prim[0] > 0.0 && p->ref_prim[4] > 0.0)) { why = "ref_prim needs rho > 0 and p > 0"; return LES_EINVAL; }
   }
   if (b[1] == LES_BC_OUTFLOW && !finite_pos(p->p_exit)) { why = "p_exit must be > 0"; return LES_EINVAL; }
-  if (p->sgs_model != LES_SGS_NONE && p->sgs_model != LES_SGS_SMAGORINSKY) { why = "unknown sgs_model"; return LES_EINVAL; }
-  if (p->sgs_model == LES_SGS_SMAGORINSKY && p->visc_coef == 0.0 && p->Cs != 0.0) {
-    why = "the Smagorinsky model needs visc_coef > 0 (mu_sgs is in units of the jet viscosity)";
+  if (p->sgs_model != LES_SGS_NONE && p->sgs_model != LES_SGS_SMAGORINSKY &&
+      p->sgs_model != LES_SGS_VREMAN) { why = "unknown sgs_model"; return LES_EINVAL; }
+  if (p->sgs_model != LES_SGS_NONE && p->visc_coef == 0.0 && p->Cs != 0.0) {
+    why = "an SGS model needs visc_coef > 0 (mu_sgs is in units of the jet viscosity)";
     return LES_EINVAL;
   }
   if (p->precision != LES_FP64 && p->precision != LES_FP32_STORAGE) { why = "unknown precision"; return LES_EINVAL; }
@@ -158,8 +159,10 @@ static Phys<T> make_phys(const les_params* p) {
   ph.suth = (T)p->suth_S;
   ph.suth1 = (T)(1.0 + p->suth_S);
   ph.viscous = p->visc_coef != 0.0;
-  ph.sgs = ph.viscous && p->sgs_model == LES_SGS_SMAGORINSKY && p->Cs != 0.0;
-  ph.Cs2_over_Cv = ph.viscous ? (T)(p->Cs * p->Cs / p->visc_coef) : T(0);
+  ph.sgs = ph.viscous && p->Cs != 0.0 ? p->sgs_model : 0;
+  // Vreman's constant is c = 2.5 Cs^2
+  const double c = p->sgs_model == LES_SGS_VREMAN ? 2.5 * p->Cs * p->Cs : p->Cs * p->Cs;
+  ph.sgs_coef = ph.sgs ? (T)(c / p->visc_coef) : T(0);
   ph.k2 = (T)p->k2;
   ph.k4 = (T)p->k4;
   for (int d = 0; d < 3; ++d)

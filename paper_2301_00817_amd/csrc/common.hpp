@@ -42,10 +42,11 @@ struct Phys {
   T Pr_inv, Prs_inv;      // 1/Pr, 1/Pr_sgs
   T Cv;                   // visc_coef = M/Re
   T suth, suth1;          // S, 1 + S (Sutherland)
-  T Cs2_over_Cv;          // Cs^2 / Cv (Smagorinsky, in jet-viscosity units)
+  T sgs_coef;             // Smagorinsky Cs^2 / Cv, Vreman 2.5 Cs^2 / Cv
+                          // (eddy viscosity in jet-viscosity units)
   T k2, k4;
   int viscous;            // Cv != 0
-  int sgs;                // Smagorinsky on
+  int sgs;                // 0 none, 1 Smagorinsky, 2 Vreman
   int phys_face[3][2];    // face -1/2 / n-1/2 along d is a physical boundary
 };
 

@@ -149,6 +149,22 @@ __host__ __device__ __forceinline__ void neighbour_terms(const T m[5], const T p
   nu = tabs(num) * trcp(den);
 }
 
+// Vreman's sqrt(B_beta / (alpha_ij alpha_ij)) divided by Delta^2, from the
+// velocity gradient g[i][m] = d u_i / d x_m (alpha_mi = g[i][m]); zero where
+// alpha_ij alpha_ij = 0 or B_beta <= 0 (rounding of a positive
+// semi-definite minor sum).
+template <typename T>
+__host__ __device__ __forceinline__ T vreman_ratio(const T g[4][3]) {
+  T b[3][3], aa = T(0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j)
+      b[i][j] = g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2];
+  for (int i = 0; i < 3; ++i) aa += b[i][i];
+  const T B = b[0][0] * b[1][1] - b[0][1] * b[0][1] + b[0][0] * b[2][2] - b[0][2] * b[0][2] +
+              b[1][1] * b[2][2] - b[1][2] * b[1][2];
+  return (aa > T(0) && B > T(0)) ? tsqrt(B * trcp(aa)) : T(0);
+}
+
 template <typename T>
 struct PointOut {
   T G[3][5];
@@ -189,7 +205,7 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
 
     const T mu = Tt * a * ph.suth1 * trcp(Tt + ph.suth);      // Sutherland
     T mut = T(0);
-    if (ph.sgs) {
+    if (ph.sgs == 1) {                                        // Smagorinsky
       T s2 = T(0);
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
@@ -197,7 +213,10 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
           s2 += sij * sij;
         }
       const T delta = tcbrt(tabs(in.V));
-      mut = s.rho * ph.Cs2_over_Cv * delta * delta * tsqrt(T(2) * s2);
+      mut = s.rho * ph.sgs_coef * delta * delta * tsqrt(T(2) * s2);
+    } else if (ph.sgs == 2) {                                 // Vreman
+      const T delta = tcbrt(tabs(in.V));
+      mut = s.rho * ph.sgs_coef * delta * delta * vreman_ratio(g);
     }
     const T mt = mu + mut;
     const T div = g[0][0] + g[1][1] + g[2][2];

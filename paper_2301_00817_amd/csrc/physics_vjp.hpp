@@ -7,6 +7,41 @@
 
 namespace lesjet {
 
+// Reverse of vreman_ratio: adds d(ratio)/d g[i][m] * rb to gb (zero where
+// the forward clipped to zero).
+template <typename T>
+__host__ __device__ inline void vreman_ratio_vjp(const T g[4][3], T rb, T gb[4][3]) {
+  T b[3][3], aa = T(0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j)
+      b[i][j] = g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2];
+  for (int i = 0; i < 3; ++i) aa += b[i][i];
+  const T B = b[0][0] * b[1][1] - b[0][1] * b[0][1] + b[0][0] * b[2][2] - b[0][2] * b[0][2] +
+              b[1][1] * b[2][2] - b[1][2] * b[1][2];
+  if (!(aa > T(0) && B > T(0))) return;
+  const T iaa = T(1) / aa;
+  const T x = B * iaa;
+  const T r = tsqrt(x);
+  const T x_b = rb / (T(2) * r);
+  const T B_b = x_b * iaa;
+  const T aa_b = -x_b * x * iaa;
+  T bb[3][3];
+  bb[0][0] = B_b * (b[1][1] + b[2][2]) + aa_b;
+  bb[1][1] = B_b * (b[0][0] + b[2][2]) + aa_b;
+  bb[2][2] = B_b * (b[0][0] + b[1][1]) + aa_b;
+  bb[0][1] = T(-2) * b[0][1] * B_b;
+  bb[0][2] = T(-2) * b[0][2] * B_b;
+  bb[1][2] = T(-2) * b[1][2] * B_b;
+  for (int m = 0; m < 3; ++m) {
+    for (int i = 0; i < 3; ++i) gb[i][m] += T(2) * bb[i][i] * g[i][m];
+    for (int i = 0; i < 3; ++i)
+      for (int j = i + 1; j < 3; ++j) {
+        gb[i][m] += bb[i][j] * g[j][m];
+        gb[j][m] += bb[i][j] * g[i][m];
+      }
+  }
+}
+
 // Cotangents of the inputs of point_quantities.
 template <typename T>
 struct PointBar {
@@ -67,13 +102,20 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
     T mut = 0, Smag = 0, Csd2 = 0, sij[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) sij[i][j] = T(0.5) * (g[i][j] + g[j][i]);
+    // mut = rho coef Delta^2 Smag with the model's shape factor Smag:
+    // sqrt(2 S_ij S_ij) (Smagorinsky) or sqrt(B_beta / alpha.alpha) / Delta^2
+    // (Vreman)
     if (ph.sgs) {
-      T s2 = 0;
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) s2 += sij[i][j] * sij[i][j];
       const T delta = tcbrt(tabs(in.V));
-      Csd2 = ph.Cs2_over_Cv * delta * delta;
-      Smag = tsqrt(T(2) * s2);
+      Csd2 = ph.sgs_coef * delta * delta;
+      if (ph.sgs == 1) {
+        T s2 = 0;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) s2 += sij[i][j] * sij[i][j];
+        Smag = tsqrt(T(2) * s2);
+      } else {
+        Smag = vreman_ratio(g);
+      }
       mut = rho * Csd2 * Smag;
     }
     const T mt = mu + mut;
@@ -116,13 +158,15 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
     mu_b += mt_b;
     mut_b += mt_b;
     if (ph.sgs) {
-      // mut = rho Csd2 Smag, Smag = sqrt(2 sum sij^2): dSmag/dg_ij = 2 sij / Smag
       rho_b += mut_b * Csd2 * Smag;
       const T Smag_b = mut_b * rho * Csd2;
-      if (Smag > T(0)) {
+      if (ph.sgs == 1 && Smag > T(0)) {
+        // Smag = sqrt(2 sum sij^2): dSmag/dg_ij = 2 sij / Smag
         const T h = Smag_b * T(2) / Smag;
         for (int i = 0; i < 3; ++i)
           for (int j = 0; j < 3; ++j) g_b[i][j] += h * sij[i][j];
+      } else if (ph.sgs == 2) {
+        vreman_ratio_vjp(g, Smag_b, g_b);
       }
     }
     // Sutherland: dmu/dT = mu (3/(2T) - 1/(T + S))

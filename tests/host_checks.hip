@@ -19,7 +19,7 @@ Phys<double> make_phys(int sgs) {
   ph.gamma = 1.4; ph.gm1 = 0.4; ph.igm1 = 1.0 / 0.4;
   ph.Pr_inv = 1.0 / 0.72; ph.Prs_inv = 1.0 / 0.9;
   ph.Cv = 0.02; ph.suth = 110.4 / 288.15; ph.suth1 = 1.0 + ph.suth;
-  ph.Cs2_over_Cv = 0.148 * 0.148 / ph.Cv;
+  ph.sgs_coef = (sgs == 2 ? 2.5 : 1.0) * 0.148 * 0.148 / ph.Cv;
   ph.k2 = 0.25; ph.k4 = 0.016;
   ph.viscous = 1; ph.sgs = sgs;
   for (int d = 0; d < 3; ++d) ph.phys_face[d][0] = ph.phys_face[d][1] = 0;

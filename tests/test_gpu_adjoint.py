@@ -6,9 +6,9 @@ test_oracle_adjoint.py).  Cases:
   * dense Jacobian on the 8x6x8 jet (every boundary kind): every row of
     dR/dQ and of dR/d(inflow data) from les_residual_vjp with unit
     cotangents, against the complex-step Jacobian, per row <= 1e-12;
-  * directional checks <Rbar, J v> = <Qbar, v> on a periodic box with the
-    SGS model, on a 24x12x16 jet and on the full 160x100x128 jet mesh with a
-    seeded Gaussian cotangent;
+  * directional checks <Rbar, J v> = <Qbar, v> on a periodic box and a
+    24x12x16 jet with the Smagorinsky and with the Vreman model, and on the
+    full 160x100x128 jet mesh with a seeded Gaussian cotangent;
   * RK5-step adjoint against complex-step derivatives of the oracle's RK5
     step (fixed dt), including the entrance-data cotangent and in-place use;
   * central differences of the GPU's own forward residual (dot-product
@@ -107,12 +107,14 @@ def test_vjp_dense_jacobian_tiny_jet():
     assert err_in.max() <= 1e-12
 
 
-@pytest.mark.parametrize("case", ["box16", "jet24x12x16"])
+@pytest.mark.parametrize("case", ["box16", "jet24x12x16", "box16_vreman", "jet24x12x16_vreman"])
 def test_vjp_directional(case):
-    if case == "box16":
+    if case.startswith("box16"):
         pb = problems.box_problem(16, seed=7, noise=1e-3)
     else:
         pb = _jet(24, 12, 16, seed=8)
+    if case.endswith("vreman"):
+        pb["params"] = dict(pb["params"], sgs_model=2)
     announce("vjp directional", case)
     geo = _geo(pb)
     Q = pb["Q"].numpy()

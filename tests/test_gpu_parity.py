@@ -51,6 +51,8 @@ CASES = {
     "box32": lambda: problems.box_problem(32),
     "box_inviscid": lambda: _with(problems.box_problem(24), visc_coef=0.0, sgs_model=0),
     "jet37x22x20_nosgs": lambda: _with(_jet(37, 22, 20), sgs_model=0),
+    "box32_vreman": lambda: _with(problems.box_problem(32), sgs_model=2),
+    "jet37x22x20_vreman": lambda: _with(_jet(37, 22, 20, perturb=0.01), sgs_model=2),
     "box32_cs018": lambda: problems.box_problem(32, Cs=0.18),
     "box_ragged": lambda: problems.box_problem(17, shape=(17, 23, 9)),
     "jet8x6x8": lambda: _jet(8, 6, 8, perturb=0.05),

@@ -26,7 +26,7 @@ def lib():
     return lib
 
 
-@pytest.mark.parametrize("sgs", [0, 1])
+@pytest.mark.parametrize("sgs", [0, 1, 2])
 def test_point_quantities_vjp(lib, sgs):
     errs = [lib.check_point_vjp(s, sgs) for s in range(1, 40)]
     assert max(errs) < 1e-6, max(errs)

@@ -40,7 +40,7 @@ __device__ __forceinline__ void load5d(const double* A, const Grid& g, int o, do
 }
 
 __device__ __forceinline__ double pressure(const double q[5], const Phys<double>& ph) {
-  const double ir = 1.0 / q[0];
+  const double ir = trcp(q[0]);
   const double u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
   return ph.gm1 * (q[4] - 0.5 * q[0] * (u * u + v * v + w * w));
 }
@@ -86,28 +86,28 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
   load5d(Q, g, o, q);
   prim5(q, ph, pr);
   for (int c = 0; c < 5; ++c) SC[(long long)(S_PR + c) * g.vs + o] = pr[c];
-  const double iV = 1.0 / M[9LL * g.vs + o];
+  const double iV = trcp(M[9LL * g.vs + o]);
   const bool inner = interior(g, i, j, k);
   for (int c = 0; c < 5; ++c)   // zero off the interior: R has no entries there
     SC[(long long)(S_RT + c) * g.vs + o] = inner ? Rb[(long long)c * g.vs + o] * iV : 0.0;
   if (!in_r1(g, i, j, k)) return;
-  const double a = sqrt(pr[3]);
+  const double a = tsqrt(pr[3]);
   const double aiV = fabs(iV);
   double lam[3];
   for (int d = 0; d < 3; ++d) {
     const double S0 = M[(long long)(3 * d) * g.vs + o], S1 = M[(long long)(3 * d + 1) * g.vs + o],
                  S2 = M[(long long)(3 * d + 2) * g.vs + o];
     const double Uc = S0 * pr[0] + S1 * pr[1] + S2 * pr[2];
-    lam[d] = (fabs(Uc) + a * sqrt(S0 * S0 + S1 * S1 + S2 * S2)) * aiV;
+    lam[d] = (fabs(Uc) + a * tsqrt(S0 * S0 + S1 * S1 + S2 * S2)) * aiV;
     double qm[5], qp[5];
     load5d(Q, g, o - step[d], qm);
     load5d(Q, g, o + step[d], qp);
     const double pm = pressure(qm, ph), pp = pressure(qp, ph);
     const double num = pp - 2.0 * pr[4] + pm, den = pp + 2.0 * pr[4] + pm;
-    SC[(long long)(S_NU + d) * g.vs + o] = fabs(num) / den;
+    SC[(long long)(S_NU + d) * g.vs + o] = fabs(num) * trcp(den);
   }
-  const double s01 = sqrt(lam[0] * lam[1]), s02 = sqrt(lam[0] * lam[2]),
-               s12 = sqrt(lam[1] * lam[2]);
+  const double s01 = tsqrt(lam[0] * lam[1]), s02 = tsqrt(lam[0] * lam[2]),
+               s12 = tsqrt(lam[1] * lam[2]);
   SC[(long long)(S_LB + 0) * g.vs + o] = lam[0] + s01 + s02;
   SC[(long long)(S_LB + 1) * g.vs + o] = lam[1] + s01 + s12;
   SC[(long long)(S_LB + 2) * g.vs + o] = lam[2] + s02 + s12;
@@ -378,13 +378,19 @@ __global__ __launch_bounds__(256) void k_adjT_eta(const double* __restrict__ Q, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_adjT_xi(const double* __restrict__ Q, const double* __restrict__ M,
+__global__ __launch_bounds__(64) void k_adjT_xi(const double* __restrict__ Q, const double* __restrict__ M,
                           double* __restrict__ Qb, Grid g, const double* __restrict__ inflow,
                           double* __restrict__ inflow_bar, double gamma, int lo_kind, int hi_kind,
                           double p_exit) {
+  // one thread per (j, k) and face: the faces touch disjoint ghosts and
+  // disjoint interior points
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.nr * g.nth) return;
-  const int j = t % g.nr, k = t / g.nr;
+  const int nf = g.nr * g.nth;
+  if (t >= 2 * nf) return;
+  const bool lo = t < nf;
+  const int jk = lo ? t : t - nf;
+  const int j = jk % g.nr, k = jk / g.nr;
+  if (!lo) { lo_kind = -1; } else { hi_kind = -1; }
   auto take = [&](int oe, int side, double fb[5]) {
     for (int c = 0; c < 5; ++c) fb[c] = 0.0;
     for (int m = 1; m <= NG; ++m) {
@@ -488,8 +494,8 @@ hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
   BPrim<double> ref = {ref_prim[0], ref_prim[1], ref_prim[2], ref_prim[3], ref_prim[4]};
   hipLaunchKernelGGL(k_adjT_eta, dim3(blocks_for((long long)(g.nx + 2 * NG) * g.nth, 256)), dim3(256),
                      0, s, Q, M, Qb, g, gamma, bc[2], bc[3], ref);
-  hipLaunchKernelGGL(k_adjT_xi, dim3(blocks_for((long long)g.nr * g.nth, 256)), dim3(256), 0, s, Q,
-                     M, Qb, g, inflow, inflow_bar, gamma, bc[0], bc[1], p_exit);
+  hipLaunchKernelGGL(k_adjT_xi, dim3(blocks_for(2LL * g.nr * g.nth, 64)), dim3(64), 0, s, Q, M, Qb,
+                     g, inflow, inflow_bar, gamma, bc[0], bc[1], p_exit);
   return hipGetLastError();
 }
 

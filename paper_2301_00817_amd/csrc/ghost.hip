@@ -36,14 +36,19 @@ __device__ __forceinline__ void unit_normal(const T* M, int vs, int o, int d, do
   n[0] = a * inv; n[1] = b * inv; n[2] = c * inv;
 }
 
-// xi faces, one thread per (j, k) of the interior.
+// xi faces, one thread per (j, k) of the interior and face (the two faces
+// read interior points only and write disjoint ghosts).
 template <typename T>
 __global__ void k_ghost_xi(T* __restrict__ Q, Grid g, const T* __restrict__ M,
                            const double* __restrict__ inflow, double gamma, int lo_kind,
                            int hi_kind, double p_exit) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.nr * g.nth) return;
-  const int j = t % g.nr, k = t / g.nr;
+  const int nf = g.nr * g.nth;
+  if (t >= 2 * nf) return;
+  const bool lo = t < nf;
+  const int jk = lo ? t : t - nf;
+  const int j = jk % g.nr, k = jk / g.nr;
+  if (!lo) { lo_kind = -1; } else { hi_kind = -1; }
   T q[5];
   if (lo_kind == BC_PERIODIC) {
     for (int m = 1; m <= NG; ++m) {
@@ -141,8 +146,8 @@ hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
                          double p_exit, hipStream_t s) {
   const int bs = 256;
   const double gamma = (double)ph.gamma;
-  hipLaunchKernelGGL(k_ghost_xi<T>, dim3(blocks_for((long long)g.nr * g.nth, bs)), dim3(bs), 0,
-                     s, Q, g, M, inflow, gamma, bc[0], bc[1], p_exit);
+  hipLaunchKernelGGL(k_ghost_xi<T>, dim3(blocks_for(2LL * g.nr * g.nth, 64)), dim3(64), 0, s, Q,
+                     g, M, inflow, gamma, bc[0], bc[1], p_exit);
   BPrim<T> ref;
   ref.rho = (T)ref_prim[0]; ref.u = (T)ref_prim[1]; ref.v = (T)ref_prim[2];
   ref.w = (T)ref_prim[3]; ref.p = (T)ref_prim[4];

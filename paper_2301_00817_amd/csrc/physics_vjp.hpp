@@ -19,10 +19,10 @@ __host__ __device__ inline void vreman_ratio_vjp(const T g[4][3], T rb, T gb[4][
   const T B = b[0][0] * b[1][1] - b[0][1] * b[0][1] + b[0][0] * b[2][2] - b[0][2] * b[0][2] +
               b[1][1] * b[2][2] - b[1][2] * b[1][2];
   if (!(aa > T(0) && B > T(0))) return;
-  const T iaa = T(1) / aa;
+  const T iaa = trcp(aa);
   const T x = B * iaa;
   const T r = tsqrt(x);
-  const T x_b = rb / (T(2) * r);
+  const T x_b = T(0.5) * rb * trcp(r);
   const T B_b = x_b * iaa;
   const T aa_b = -x_b * x * iaa;
   T bb[3][3];
@@ -60,7 +60,7 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
   const T rho = in.q[0], u = in.pr[0], v = in.pr[1], w = in.pr[2], Tt = in.pr[3], p = in.pr[4];
   const T vel[3] = {u, v, w};
   const T a = tsqrt(Tt);
-  const T ia = T(1) / a;                       // 1/T = ia^2
+  const T ia = trcp(a);                       // 1/T = ia^2
   const T iV = trcp(in.V);
   const T aiV = tabs(iV);
   T Uc[3], Uc_b[3] = {0, 0, 0};
@@ -82,9 +82,9 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
     const T s01_b = lbb[0] + lbb[1], s02_b = lbb[0] + lbb[2], s12_b = lbb[1] + lbb[2];
     T lam_b[3] = {lbb[0], lbb[1], lbb[2]};
     // d sqrt(x y)/dx = y / (2 sqrt(x y))
-    if (s01 > T(0)) { const T h = s01_b / (T(2) * s01); lam_b[0] += h * lam[1]; lam_b[1] += h * lam[0]; }
-    if (s02 > T(0)) { const T h = s02_b / (T(2) * s02); lam_b[0] += h * lam[2]; lam_b[2] += h * lam[0]; }
-    if (s12 > T(0)) { const T h = s12_b / (T(2) * s12); lam_b[1] += h * lam[2]; lam_b[2] += h * lam[1]; }
+    if (s01 > T(0)) { const T h = T(0.5) * s01_b * trcp(s01); lam_b[0] += h * lam[1]; lam_b[1] += h * lam[0]; }
+    if (s02 > T(0)) { const T h = T(0.5) * s02_b * trcp(s02); lam_b[0] += h * lam[2]; lam_b[2] += h * lam[0]; }
+    if (s12 > T(0)) { const T h = T(0.5) * s12_b * trcp(s12); lam_b[1] += h * lam[2]; lam_b[2] += h * lam[1]; }
     for (int d = 0; d < 3; ++d) {
       Uc_b[d] += lam_b[d] * aiV * (Uc[d] < T(0) ? T(-1) : T(1));
       a_b += lam_b[d] * Sn[d] * aiV;
@@ -97,7 +97,7 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
     for (int f = 0; f < 4; ++f)
       for (int m = 0; m < 3; ++m)
         g[f][m] = (in.S[0][m] * dl[0][f] + in.S[1][m] * dl[1][f] + in.S[2][m] * dl[2][f]) * iV;
-    const T iTS = T(1) / (Tt + ph.suth);
+    const T iTS = trcp(Tt + ph.suth);
     const T mu = Tt * a * ph.suth1 * iTS;
     T mut = 0, Smag = 0, Csd2 = 0, sij[3][3];
     for (int i = 0; i < 3; ++i)
@@ -162,7 +162,7 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
       const T Smag_b = mut_b * rho * Csd2;
       if (ph.sgs == 1 && Smag > T(0)) {
         // Smag = sqrt(2 sum sij^2): dSmag/dg_ij = 2 sij / Smag
-        const T h = Smag_b * T(2) / Smag;
+        const T h = T(2) * Smag_b * trcp(Smag);
         for (int i = 0; i < 3; ++i)
           for (int j = 0; j < 3; ++j) g_b[i][j] += h * sij[i][j];
       } else if (ph.sgs == 2) {
@@ -208,7 +208,7 @@ __host__ __device__ inline void point_quantities_vjp(const PointIn<T>& in, const
 template <typename T>
 __host__ __device__ inline void prim5_vjp(const T q[5], const Phys<T>& ph, const T prb[5],
                                           T qb[5]) {
-  const T ir = T(1) / q[0];
+  const T ir = trcp(q[0]);
   const T u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
   const T p = ph.gm1 * (q[4] - T(0.5) * q[0] * (u * u + v * v + w * w));
   // T = gamma p ir
@@ -234,7 +234,7 @@ __host__ __device__ inline void prim5_vjp(const T q[5], const Phys<T>& ph, const
 template <typename T>
 __host__ __device__ inline void sensor_vjp(T pm, T p0, T pp, T nb, T& side, T& centre) {
   const T num = pp - T(2) * p0 + pm;
-  const T iden = T(1) / (pp + T(2) * p0 + pm);
+  const T iden = trcp(pp + T(2) * p0 + pm);
   const T nu = tabs(num) * iden;
   const T sg = num < T(0) ? T(-1) : T(1);
   side = nb * (sg - nu) * iden;

@@ -101,3 +101,33 @@ def test_big_mesh_layout_fits_32bit_offsets():
     pitch, dims, vs = B.les_layout(p)
     assert vs < 2 ** 31
     assert 5 * vs > 2 ** 32          # whole fields need 64-bit bases
+
+
+@pytest.mark.parametrize("call", [
+    "les_residual", "les_residual_reference", "les_fill_ghosts", "les_metrics",
+    "les_rk5_step", "les_residual_vjp", "les_rk5_step_vjp", "les_diagnostics",
+    "les_profile", "les_profile_read", "les_query",
+])
+def test_entry_points_reject_a_null_context(call):
+    """Every entry point taking a context returns LES_EINVAL for NULL before
+    any device work (no GPU is touched here)."""
+    from paper_2301_00817_amd import binding as B
+    fn = getattr(B, call)
+    args = {
+        "les_residual": (None, None, None), "les_residual_reference": (None, None, None),
+        "les_fill_ghosts": (None, None), "les_metrics": (None,),
+        "les_rk5_step": (None, None, 1, 0.0), "les_residual_vjp": (None, None, None, None),
+        "les_rk5_step_vjp": (None, None, 1e-3, None, None), "les_diagnostics": (None, None),
+        "les_profile": (None, 1), "les_profile_read": (None,), "les_query": (None,),
+    }[call]
+    with pytest.raises(B.LesError) as e:
+        fn(*args)
+    assert e.value.code == B.LES_EINVAL
+
+
+def test_validate_accepts_every_sgs_model():
+    from paper_2301_00817_amd import binding as B
+    for m in (0, 1, 2, "none", "smagorinsky", "vreman"):
+        assert B.les_validate(_params(sgs_model=m)) == 0
+    with pytest.raises(B.LesError):
+        B.les_validate(_params(sgs_model=2, visc_coef=0.0))

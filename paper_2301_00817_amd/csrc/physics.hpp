@@ -59,10 +59,26 @@ template <> __host__ __device__ __forceinline__ double tsqrt<double>(double x) {
 #else
 template <> __host__ __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
 #endif
+// FP32 (the storage form only): the hardware square root and a cube root
+// from the hardware base-2 logarithm and exponential, each within a few ulps
+// of FP32, far inside that form's tolerances.
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(LESJET_IEEE_F32)
+template <> __host__ __device__ __forceinline__ float tsqrt<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x);
+}
+#else
 template <> __host__ __device__ __forceinline__ float tsqrt<float>(float x) { return sqrtf(x); }
+#endif
 template <typename T> __host__ __device__ __forceinline__ T tcbrt(T x);
 template <> __host__ __device__ __forceinline__ double tcbrt<double>(double x) { return cbrt(x); }
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(LESJET_IEEE_F32)
+template <> __host__ __device__ __forceinline__ float tcbrt<float>(float x) {
+  // x > 0 here (|J^-1|); exp2(log2(x) / 3)
+  return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
+}
+#else
 template <> __host__ __device__ __forceinline__ float tcbrt<float>(float x) { return cbrtf(x); }
+#endif
 template <typename T> __host__ __device__ __forceinline__ T tpow(T x, T y);
 template <> __host__ __device__ __forceinline__ double tpow<double>(double x, double y) { return pow(x, y); }
 template <> __host__ __device__ __forceinline__ float tpow<float>(float x, float y) { return powf(x, y); }

@@ -1,0 +1,72 @@
+"""Error paths of the C-ABI that need a device context.  Every failure here
+is forced from the host (a NaN in the state, an out-of-order call, an
+unsupported precision, a bad argument); no kernel is made to fault."""
+import math
+
+import pytest
+import torch
+
+from _helpers import announce, make_solver
+from cases import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_nonfinite_state_is_reported(precision):
+    """A NaN in the state reaches the CFL reduction, which is NaN-sticky:
+    les_rk5_step returns LES_ENONFINITE."""
+    from paper_2301_00817_amd import binding as B
+    announce("non-finite state", precision)
+    pb = problems.box_problem(16)
+    s = make_solver(pb, precision=precision)
+    Q = pb["Q"].clone()
+    Q[0, 3, 4, 5] = float("nan")
+    Qn = s.pad(Q.cuda(), dtype=torch.float64)
+    with pytest.raises(B.LesError) as e:
+        s.rk5_step(Qn, 2)
+    assert e.value.code == B.LES_ENONFINITE
+    # the context stays usable: a finite state steps normally afterwards
+    Qn = s.pad(pb["Q"].cuda(), dtype=torch.float64)
+    dt = s.rk5_step(Qn, 1)
+    assert math.isfinite(float(dt[0])) and float(dt[0]) > 0.0
+    s.close()
+
+
+def test_call_order_and_arguments():
+    from paper_2301_00817_amd import binding as B
+    announce("call order and arguments")
+    pb = problems.jet_problem(12, 8, 8)
+    p = B.make_params(pb["params"], (12, 8, 8), B.LES_FP64)
+    xyz = pb["xyz"].cuda().contiguous()
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = B.les_init_grid(p, xyz.data_ptr(), stream)
+    try:
+        _, dims, _ = B.les_layout(p)
+        Q = torch.zeros((5,) + dims, dtype=torch.float64, device="cuda")
+        R = torch.zeros_like(Q)
+        with pytest.raises(B.LesError) as e:           # before les_metrics
+            B.les_residual(ctx, Q.data_ptr(), R.data_ptr(), stream)
+        assert e.value.code == B.LES_ESTATE
+        B.les_metrics(ctx, None, stream)
+        with pytest.raises(B.LesError) as e:           # entrance data missing
+            B.les_residual(ctx, Q.data_ptr(), R.data_ptr(), stream)
+        assert e.value.code == B.LES_ESTATE
+        inflow = pb["inflow"].cuda().contiguous()
+        B.les_set_inflow(ctx, inflow.data_ptr(), stream)
+        with pytest.raises(B.LesError) as e:           # aliasing
+            B.les_residual(ctx, Q.data_ptr(), Q.data_ptr(), stream)
+        assert e.value.code == B.LES_EINVAL
+        with pytest.raises(B.LesError) as e:           # metrics twice
+            B.les_metrics(ctx, None, stream)
+        assert e.value.code == B.LES_ESTATE
+        with pytest.raises(B.LesError) as e:           # the step adjoint needs dt > 0
+            B.les_rk5_step_vjp(ctx, Q.data_ptr(), 0.0, R.data_ptr(), R.data_ptr(), None, stream)
+        assert e.value.code == B.LES_EINVAL
+        with pytest.raises(B.LesError) as e:
+            B.les_rk5_step(ctx, Q.data_ptr(), -1, 0.0, None, stream)
+        assert e.value.code == B.LES_EINVAL
+        assert B.les_last_error(ctx)
+    finally:
+        B.les_free(ctx)
+    torch.cuda.synchronize()

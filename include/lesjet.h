@@ -130,7 +130,9 @@ int les_device_bytes(const les_params* p, size_t* bytes);
  * The coordinates are copied; `xyz` may be freed after the call returns
  * (the call synchronises `stream`).  The environment variable LESJET_KCHUNK,
  * if set to a positive integer, overrides the number of azimuthal planes
- * one block of the fused kernel marches over (tuning and tests).
+ * one block of the fused kernel marches over (tuning and tests); with
+ * LESJET_POISON=1 every device buffer the library allocates is filled with
+ * NaN bit patterns (a test hook that exposes reads of unwritten memory).
  * Section "Transformation of
  * Coordinates"; the centerline and periodic subsections of "Boundary
  * Conditions". */

@@ -90,7 +90,14 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
   const bool inner = interior(g, i, j, k);
   for (int c = 0; c < 5; ++c)   // zero off the interior: R has no entries there
     SC[(long long)(S_RT + c) * g.vs + o] = inner ? Rb[(long long)c * g.vs + o] * iV : 0.0;
-  if (!in_r1(g, i, j, k)) return;
+  if (!in_r1(g, i, j, k)) {
+    // no face uses these; written so that no pass reads unset memory
+    for (int d = 0; d < 3; ++d) {
+      SC[(long long)(S_LB + d) * g.vs + o] = 0.0;
+      SC[(long long)(S_NU + d) * g.vs + o] = 0.0;
+    }
+    return;
+  }
   const double a = tsqrt(pr[3]);
   const double aiV = fabs(iV);
   double lam[3];
@@ -123,22 +130,20 @@ struct FaceCoef {
   bool dis;       // the face carries dissipation
 };
 
-__device__ __forceinline__ void face_coef(const double* SC, const double* M, const Grid& g,
-                                          const Phys<double>& ph, int d, int L, int n, int oL,
-                                          int sd, FaceCoef& f) {
-  const int oR = oL + sd;
-  for (int c = 0; c < 5; ++c)      // S_RT is zero off the interior
-    f.Fb[c] = SC[(long long)(S_RT + c) * g.vs + oL] - SC[(long long)(S_RT + c) * g.vs + oR];
-  f.dis = !((L == -1 && ph.phys_face[d][0]) || (L == n - 1 && ph.phys_face[d][1]));
-  if (!f.dis) return;
-  const double nuL = SC[(long long)(S_NU + d) * g.vs + oL];
-  const double nuR = SC[(long long)(S_NU + d) * g.vs + oR];
-  f.lf = 0.5 * (SC[(long long)(S_LB + d) * g.vs + oL] + SC[(long long)(S_LB + d) * g.vs + oR]);
-  f.Vf = 0.5 * (M[9LL * g.vs + oL] + M[9LL * g.vs + oR]);
-  f.nu_left = nuL >= nuR;
-  f.e2 = ph.k2 * fmax(nuL, nuR);
-  f.k4m = ph.k4 - f.e2;
-  f.e4 = fmax(0.0, f.k4m);
+// Face L | L+1 from the line arrays (line points f and f+1).  Only the
+// coefficients of existing faces (L in [-1, n-1]) are used by the caller.
+__device__ __forceinline__ void line_face(const double rt[5][5], const double lbl[5],
+                                          const double nul[5], const double vl[5], int f, int d,
+                                          int L, int n, const Phys<double>& ph, FaceCoef& fc) {
+  for (int c = 0; c < 5; ++c) fc.Fb[c] = rt[f][c] - rt[f + 1][c];   // S_RT is zero off the interior
+  fc.dis = !((L == -1 && ph.phys_face[d][0]) || (L == n - 1 && ph.phys_face[d][1]));
+  const double nuL = nul[f], nuR = nul[f + 1];
+  fc.lf = 0.5 * (lbl[f] + lbl[f + 1]);
+  fc.Vf = 0.5 * (vl[f] + vl[f + 1]);
+  fc.nu_left = nuL >= nuR;
+  fc.e2 = ph.k2 * fmax(nuL, nuR);
+  fc.k4m = ph.k4 - fc.e2;
+  fc.e4 = fmax(0.0, fc.k4m);
 }
 
 // Reverse of the dissipation of a face at one of its two inner points:
@@ -192,33 +197,40 @@ __global__ __launch_bounds__(256) void k_adj_main(const double* __restrict__ Q,
     const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
     if (pos[d1] < 0 || pos[d1] >= nn[d1] || pos[d2] < 0 || pos[d2] >= nn[d2]) continue;
     const int s = pos[d], sd = step[d], n = nn[d];
+    // the line p-2 .. p+2 along d (points outside the padded box, reached
+    // only when p is a ghost, are clamped to its edge; no existing face uses
+    // them); face L = s-2+f joins line points f and f+1
+    double rt[5][5], lbl[5], nul[5], vl[5];
+    for (int m = 0; m < 5; ++m) {
+      const int pt = min(max(s + m - 2, -NG), n - 1 + NG);
+      const int om = o + (pt - s) * sd;
+      for (int c = 0; c < 5; ++c) rt[m][c] = SC[(long long)(S_RT + c) * g.vs + om];
+      lbl[m] = SC[(long long)(S_LB + d) * g.vs + om];
+      nul[m] = SC[(long long)(S_NU + d) * g.vs + om];
+      vl[m] = M[9LL * g.vs + om];
+    }
+    FaceCoef fo[2], fb, fc;
+    // faces exist for L in [-1, n-1]
+    const bool ha = s - 2 >= -1, hd = s + 1 <= n - 1;
+    const bool hb = s - 1 >= -1 && s - 1 <= n - 1, hc = s >= -1 && s <= n - 1;
+    line_face(rt, lbl, nul, vl, 0, d, s - 2, n, ph, fo[0]);
+    line_face(rt, lbl, nul, vl, 3, d, s + 1, n, ph, fo[1]);
+    line_face(rt, lbl, nul, vl, 1, d, s - 1, n, ph, fb);
+    line_face(rt, lbl, nul, vl, 2, d, s, n, ph, fc);
     // faces L = s-2 and s+1: p is the outer point of their 4-point stencil
-    if (s - 2 >= -1) {
-      FaceCoef f;
-      face_coef(SC, M, g, ph, d, s - 2, n, o - 2 * sd, sd, f);
-      if (f.dis)
-        for (int c = 0; c < 5; ++c) wb[c] += f.lf * f.e4 * f.Vf * f.Fb[c];
-    }
-    if (s + 1 <= n - 1) {
-      FaceCoef f;
-      face_coef(SC, M, g, ph, d, s + 1, n, o + sd, sd, f);
-      if (f.dis)
-        for (int c = 0; c < 5; ++c) wb[c] -= f.lf * f.e4 * f.Vf * f.Fb[c];
-    }
+    if (ha && fo[0].dis)
+      for (int c = 0; c < 5; ++c) wb[c] += fo[0].lf * fo[0].e4 * fo[0].Vf * fo[0].Fb[c];
+    if (hd && fo[1].dis)
+      for (int c = 0; c < 5; ++c) wb[c] -= fo[1].lf * fo[1].e4 * fo[1].Vf * fo[1].Fb[c];
     // faces L = s-1 (p is its right point) and L = s (p is its left point)
-    FaceCoef fb, fc;
-    const bool hb = s - 1 >= -1, hc = s <= n - 1;
-    if (hb) face_coef(SC, M, g, ph, d, s - 1, n, o - sd, sd, fb);
-    if (hc) face_coef(SC, M, g, ph, d, s, n, o, sd, fc);
     for (int c = 0; c < 5; ++c)
       gb[d][c] = 0.5 * ((hb ? fb.Fb[c] : 0.0) + (hc ? fc.Fb[c] : 0.0));
     const bool db = hb && fb.dis, dc = hc && fc.dis;
     if (db || dc) {
-      // W on the line p-2 .. p+2; points outside the padded box (s = -1 or
-      // n) belong to no dissipative face stencil and are never used
+      // W on the line p-2 .. p+2, clamped like the other line values
       double W[5][5];
       for (int m = 0; m < 5; ++m) {
-        const int pt = min(max(s + m - 2, -NG), n - 1 + NG);   // clamped: unused then
+        const int pt = min(max(s + m - 2, -NG), n - 1 + NG);
         const int om = o + (pt - s) * sd;
         load5d(Q, g, om, W[m]);
         W[m][4] += SC[(long long)(S_PR + 4) * g.vs + om];

@@ -240,3 +240,31 @@ def test_vjp_bitwise_reproducible_and_fp32_refused():
     with pytest.raises(B.LesError) as ei:
         s32.residual_vjp(Q32, a)
     assert ei.value.code == B.LES_EUNSUPPORTED
+
+
+def test_vjp_and_step_with_poisoned_buffers(monkeypatch):
+    """Every library buffer starts as NaN (LESJET_POISON=1): the residual,
+    an RK5 step and both adjoints still match their values in a context
+    whose buffers start as the allocator left them, bit for bit — no pass
+    reads memory another pass has not written."""
+    pb = _jet(24, 12, 16, seed=8)
+    announce("poisoned buffers")
+    Q = pb["Q"].cuda()
+    Rb = problems.seeded_field(tuple(Q.shape), 3, flow.FIELD_COTANGENT).cuda()
+    out = []
+    for poison in ("0", "1"):
+        monkeypatch.setenv("LESJET_POISON", poison)
+        s = make_solver(pb)
+        Qp = s.pad(Q)
+        R = s.residual(Qp, s.field(5, fill=0.0)).clone()
+        ib = s.new_inflow_bar()
+        Qb = s.residual_vjp(Qp, s.pad(Rb, fill=0.0), inflow_bar=ib).clone()
+        ib2 = s.new_inflow_bar()
+        Qb2 = s.rk5_step_vjp(Qp, 1e-4, s.pad(Rb, fill=0.0), inflow_bar=ib2).clone()
+        Q1 = s.pad(Q)
+        s.rk5_step(Q1, 2)
+        out.append([s.interior(R), s.interior(Qb), ib, s.interior(Qb2), ib2, s.interior(Q1)])
+        s.close()
+    for a, b in zip(*out):
+        assert bool(torch.isfinite(b).all())
+        assert torch.equal(a, b)

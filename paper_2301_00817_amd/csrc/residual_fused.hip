@@ -50,6 +50,16 @@ template <> struct Tile<float> { static constexpr int X = 32, Y = 8, PER_CU = 3;
 
 constexpr int NPQ = 8;                // G(5), lambda_bar, nu, V per direction
 
+// LDS buffers of the plane state: two where the LDS budget allows it (FP32),
+// one for FP64 (two blocks of 59 KB per CU leave no room for a second).
+template <typename T> struct PlaneBuffers;
+#if defined(LESJET_DBUF32)
+template <> struct PlaneBuffers<float> { static constexpr int n = LESJET_DBUF32; };
+#else
+template <> struct PlaneBuffers<float> { static constexpr int n = 2; };
+#endif
+template <> struct PlaneBuffers<double> { static constexpr int n = 1; };
+
 enum { EPI_R = 0, EPI_RK = 1, EPI_RK_LAST = 2 };
 
 template <typename T>
@@ -105,8 +115,11 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
   constexpr int FR_X = FB_X + 2;                // ring-2 tile
   constexpr int FR_Y = FB_Y + 2;
   constexpr int NBORDER = FR_X * FR_Y - FB_X * FB_Y;   // ring-2 points without a thread
-  __shared__ T sQ[5][FR_Y][FR_X];
-  __shared__ T sP[5][FR_Y][FR_X];
+  // plane state and primitives; with two buffers (NB = 2) the next plane is
+  // written while the current one is still being read, saving a barrier
+  constexpr int NB = PlaneBuffers<T>::n;
+  __shared__ T sQb[NB][5][FR_Y][FR_X];
+  __shared__ T sPb[NB][5][FR_Y][FR_X];
   __shared__ T sX[NPQ][FB_Y][FB_X];
   __shared__ T sE[NPQ][FB_Y][FB_X];
   __shared__ double sRed[(FB_X * FB_Y + 63) / 64];
@@ -165,8 +178,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     prim5(q, ph, pc);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      sQ[c][ty + 1][tx + 1] = q[c];
-      sP[c][ty + 1][tx + 1] = pc[c];
+      sQb[0][c][ty + 1][tx + 1] = q[c];
+      sPb[0][c][ty + 1][tx + 1] = pc[c];
     }
     load_q(Qin, g, i, j, k0, Qd);
     prim5(Qd, ph, Pd);
@@ -181,13 +194,18 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     prim5(bq, ph, bp);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      sQ[c][bry][brx] = bq[c];
-      sP[c][bry][brx] = bp[c];
+      sQb[0][c][bry][brx] = bq[c];
+      sPb[0][c][bry][brx] = bp[c];
     }
   }
 
   for (int kk = k0 - 1; kk <= k1; ++kk) {
     const bool more = kk < k1;
+    const int cur = NB == 2 ? ((kk - k0 + 1) & 1) : 0;
+    T (*sQ)[FR_Y][FR_X] = sQb[cur];
+    T (*sP)[FR_Y][FR_X] = sPb[cur];
+    T (*nQ)[FR_Y][FR_X] = sQb[NB == 2 ? cur ^ 1 : 0];
+    T (*nP)[FR_Y][FR_X] = sPb[NB == 2 ? cur ^ 1 : 0];
     // own-column and metric loads of the next plane, in flight during (b)
     if (more) {
       if (kk + 2 <= k1 + 1) load_q(Qin, g, i, j, kk + 2, Qn);
@@ -336,13 +354,13 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     lbz = po.lb[2];
     nuz = po.nu[2];
     Vz = in.V;
-    __syncthreads();
+    if (NB == 1) __syncthreads();      // plane kk is read until here
     if (more) {
       // plane kk+1 goes to LDS: own column and ring-2 border
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        sQ[c][ty + 1][tx + 1] = Qd[c];
-        sP[c][ty + 1][tx + 1] = Pd[c];
+        nQ[c][ty + 1][tx + 1] = Qd[c];
+        nP[c][ty + 1][tx + 1] = Pd[c];
         Qd[c] = Qn[c];
       }
       if (has_b) {
@@ -350,8 +368,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
         prim5(Bn, ph, bp);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-          sQ[c][bry][brx] = Bn[c];
-          sP[c][bry][brx] = bp[c];
+          nQ[c][bry][brx] = Bn[c];
+          nP[c][bry][brx] = bp[c];
         }
       }
       prim5(Qd, ph, Pd);

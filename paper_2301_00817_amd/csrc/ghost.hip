@@ -1,6 +1,6 @@
 // Ghost layers of the state from the boundary conditions (section "Boundary
-// Conditions"), filled in the order xi, eta, zeta so that edge ghosts read
-// values that are already set:
+// Conditions"), defined as sweeps in the order xi, eta, zeta so that edge
+// ghosts take values that are already set:
 //   xi-  periodic | entrance: target imposed when its normal Mach >= 1, else
 //        Riemann invariants with the target as outside state;
 //   xi+  periodic | exit: copy when supersonic, else interior rho, u, v, w
@@ -36,126 +36,120 @@ __device__ __forceinline__ void unit_normal(const T* M, int vs, int o, int d, do
   n[0] = a * inv; n[1] = b * inv; n[2] = c * inv;
 }
 
-// xi faces, one thread per (j, k) of the interior and face (the two faces
-// read interior points only and write disjoint ghosts).
+// The fill is defined as three sweeps in the order xi (j, k interior), eta
+// (i padded, k interior), zeta (i, j padded), each reading what the earlier
+// ones wrote.  One launch evaluates it directly: every ghost point traces
+// its value back through the sweeps (zeta wrap, then the eta rule, then the
+// xi rule) to interior points, so all ghost points are independent and
+// filled in parallel.
+
+// State of (i, j, k), i padded, j and k interior, after the xi sweep.
 template <typename T>
-__global__ void k_ghost_xi(T* __restrict__ Q, Grid g, const T* __restrict__ M,
-                           const double* __restrict__ inflow, double gamma, int lo_kind,
-                           int hi_kind, double p_exit) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nf = g.nr * g.nth;
-  if (t >= 2 * nf) return;
-  const bool lo = t < nf;
-  const int jk = lo ? t : t - nf;
-  const int j = jk % g.nr, k = jk / g.nr;
-  if (!lo) { lo_kind = -1; } else { hi_kind = -1; }
-  T q[5];
-  if (lo_kind == BC_PERIODIC) {
-    for (int m = 1; m <= NG; ++m) {
-      load5(Q, g.vs, g.at(g.nx - m, j, k), q);
-      store5(Q, g.vs, g.at(-m, j, k), q);
+__device__ __forceinline__ void xi_value(const T* __restrict__ Q, const Grid& g,
+                                         const T* __restrict__ M,
+                                         const double* __restrict__ inflow, double gamma,
+                                         int lo_kind, int hi_kind, double p_exit, int i, int j,
+                                         int k, T q[5]) {
+  if (i >= 0 && i < g.nx) {
+    load5(Q, g.vs, g.at(i, j, k), q);
+  } else if (i < 0) {
+    if (lo_kind == BC_PERIODIC) {
+      load5(Q, g.vs, g.at(i + g.nx, j, k), q);
+    } else {                                   // entrance: both layers get the face state
+      const int oe = g.at(0, j, k);
+      T qe[5];
+      load5(Q, g.vs, oe, qe);
+      double n[3];
+      unit_normal(M, g.vs, oe, 0, -1.0, n);
+      BPrim<T> tg;
+      const long long sp = (long long)g.nth * g.nr, it = (long long)k * g.nr + j;
+      tg.rho = (T)inflow[0 * sp + it];
+      tg.u = (T)inflow[1 * sp + it];
+      tg.v = (T)inflow[2 * sp + it];
+      tg.w = (T)inflow[3 * sp + it];
+      tg.p = (T)inflow[4 * sp + it];
+      bc_inflow(qe, tg, n, gamma, q);
     }
-  } else if (lo_kind == BC_INFLOW) {
-    const int oe = g.at(0, j, k);
-    T qe[5];
-    load5(Q, g.vs, oe, qe);
-    double n[3];
-    unit_normal(M, g.vs, oe, 0, -1.0, n);
-    BPrim<T> tg;
-    const long long sp = (long long)g.nth * g.nr, it = (long long)k * g.nr + j;
-    tg.rho = (T)inflow[0 * sp + it];
-    tg.u = (T)inflow[1 * sp + it];
-    tg.v = (T)inflow[2 * sp + it];
-    tg.w = (T)inflow[3 * sp + it];
-    tg.p = (T)inflow[4 * sp + it];
-    bc_inflow(qe, tg, n, gamma, q);
-    for (int m = 1; m <= NG; ++m) store5(Q, g.vs, g.at(-m, j, k), q);
-  }
-  if (hi_kind == BC_PERIODIC) {
-    for (int m = 1; m <= NG; ++m) {
-      load5(Q, g.vs, g.at(m - 1, j, k), q);
-      store5(Q, g.vs, g.at(g.nx - 1 + m, j, k), q);
+  } else {
+    if (hi_kind == BC_PERIODIC) {
+      load5(Q, g.vs, g.at(i - g.nx, j, k), q);
+    } else {                                   // exit
+      const int oe = g.at(g.nx - 1, j, k);
+      T qe[5];
+      load5(Q, g.vs, oe, qe);
+      double n[3];
+      unit_normal(M, g.vs, oe, 0, 1.0, n);
+      bc_outflow(qe, n, gamma, p_exit, q);
     }
-  } else if (hi_kind == BC_OUTFLOW) {
-    const int oe = g.at(g.nx - 1, j, k);
-    T qe[5];
-    load5(Q, g.vs, oe, qe);
-    double n[3];
-    unit_normal(M, g.vs, oe, 0, 1.0, n);
-    bc_outflow(qe, n, gamma, p_exit, q);
-    for (int m = 1; m <= NG; ++m) store5(Q, g.vs, g.at(g.nx - 1 + m, j, k), q);
   }
 }
 
-// eta faces, one thread per (i, k), i over the padded range, k interior.
+// One thread per ghost point: the zeta layers of the whole padded plane, the
+// eta layers (i padded, k interior), the xi layers (j, k interior).
 template <typename T>
-__global__ void k_ghost_eta(T* __restrict__ Q, Grid g, const T* __restrict__ M, double gamma,
-                            int lo_kind, int hi_kind, BPrim<T> ref) {
-  const int NX = g.nx + 2 * NG;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= NX * g.nth) return;
-  const int i = t % NX - NG, k = t / NX;
-  T q[5];
-  if (lo_kind == BC_PERIODIC) {
-    for (int m = 1; m <= NG; ++m) {
-      load5(Q, g.vs, g.at(i, g.nr - m, k), q);
-      store5(Q, g.vs, g.at(i, -m, k), q);
-    }
-  } else if (lo_kind == BC_AXIS) {
-    const int kk = (k + g.nth / 2) % g.nth;
-    for (int m = 1; m <= NG; ++m) {
-      load5(Q, g.vs, g.at(i, m - 1, kk), q);
-      store5(Q, g.vs, g.at(i, -m, k), q);
-    }
-  }
-  if (hi_kind == BC_PERIODIC) {
-    for (int m = 1; m <= NG; ++m) {
-      load5(Q, g.vs, g.at(i, m - 1, k), q);
-      store5(Q, g.vs, g.at(i, g.nr - 1 + m, k), q);
-    }
-  } else if (hi_kind == BC_FARFIELD) {
-    const int oe = g.at(i, g.nr - 1, k);
-    T qe[5];
-    load5(Q, g.vs, oe, qe);
-    double n[3];
-    unit_normal(M, g.vs, oe, 1, 1.0, n);
-    bc_farfield(qe, ref, n, gamma, q);
-    for (int m = 1; m <= NG; ++m) store5(Q, g.vs, g.at(i, g.nr - 1 + m, k), q);
-  }
-}
-
-// zeta faces (periodic), one thread per (i, j) of the padded plane.
-template <typename T>
-__global__ void k_ghost_zeta(T* __restrict__ Q, Grid g) {
+__global__ void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
+                            const double* __restrict__ inflow, double gamma, int xlo, int xhi,
+                            int elo, int ehi, double p_exit, BPrim<T> ref) {
   const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= NX * NR) return;
-  const int i = t % NX - NG, j = t / NX - NG;
-  T q[5];
-  for (int m = 1; m <= NG; ++m) {
-    load5(Q, g.vs, g.at(i, j, g.nth - m), q);
-    store5(Q, g.vs, g.at(i, j, -m), q);
-    load5(Q, g.vs, g.at(i, j, m - 1), q);
-    store5(Q, g.vs, g.at(i, j, g.nth - 1 + m), q);
+  const long long nz = 2LL * NG * NX * NR, ne = 2LL * NG * NX * g.nth, nxg = 2LL * NG * g.nr * g.nth;
+  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t < nz) {
+    i = (int)(t % NX) - NG;
+    j = (int)((t / NX) % NR) - NG;
+    const int l = (int)(t / ((long long)NX * NR));      // 0..3 -> -2, -1, nth, nth+1
+    k = l < NG ? l - NG : g.nth + (l - NG);
+  } else if ((t -= nz) < ne) {
+    i = (int)(t % NX) - NG;
+    const int l = (int)((t / NX) % (2 * NG));
+    j = l < NG ? l - NG : g.nr + (l - NG);
+    k = (int)(t / ((long long)NX * 2 * NG));
+  } else if ((t -= ne) < nxg) {
+    const int l = (int)(t % (2 * NG));
+    i = l < NG ? l - NG : g.nx + (l - NG);
+    j = (int)((t / (2 * NG)) % g.nr);
+    k = (int)(t / (2LL * NG * g.nr));
+  } else {
+    return;
   }
+  const int og = g.at(i, j, k);
+  // zeta sweep (periodic): the wrapped point
+  int kw = k < 0 ? k + g.nth : (k >= g.nth ? k - g.nth : k);
+  // eta sweep
+  T q[5];
+  if (j >= 0 && j < g.nr) {
+    xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, j, kw, q);
+  } else if (j < 0) {
+    if (elo == BC_PERIODIC)
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, j + g.nr, kw, q);
+    else                                         // across the axis
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, -1 - j, (kw + g.nth / 2) % g.nth, q);
+  } else {
+    if (ehi == BC_PERIODIC) {
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, j - g.nr, kw, q);
+    } else {                                     // far field from the state at (i, nr-1)
+      T qe[5];
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, g.nr - 1, kw, qe);
+      double n[3];
+      unit_normal(M, g.vs, g.at(i, g.nr - 1, kw), 1, 1.0, n);
+      bc_farfield(qe, ref, n, gamma, q);
+    }
+  }
+  store5(Q, g.vs, og, q);
 }
 
 template <typename T>
 hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
                          const Phys<T>& ph, const int bc[6], const double ref_prim[5],
                          double p_exit, hipStream_t s) {
-  const int bs = 256;
   const double gamma = (double)ph.gamma;
-  hipLaunchKernelGGL(k_ghost_xi<T>, dim3(blocks_for(2LL * g.nr * g.nth, 64)), dim3(64), 0, s, Q,
-                     g, M, inflow, gamma, bc[0], bc[1], p_exit);
   BPrim<T> ref;
   ref.rho = (T)ref_prim[0]; ref.u = (T)ref_prim[1]; ref.v = (T)ref_prim[2];
   ref.w = (T)ref_prim[3]; ref.p = (T)ref_prim[4];
-  hipLaunchKernelGGL(k_ghost_eta<T>, dim3(blocks_for((long long)(g.nx + 2 * NG) * g.nth, bs)),
-                     dim3(bs), 0, s, Q, g, M, gamma, bc[2], bc[3], ref);
-  hipLaunchKernelGGL(k_ghost_zeta<T>,
-                     dim3(blocks_for((long long)(g.nx + 2 * NG) * (g.nr + 2 * NG), bs)), dim3(bs),
-                     0, s, Q, g);
+  const long long NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
+  const long long n = 2LL * NG * (NX * NR + NX * g.nth + (long long)g.nr * g.nth);
+  hipLaunchKernelGGL(k_ghost_all<T>, dim3(blocks_for(n, 128)), dim3(128), 0, s, Q, g, M, inflow,
+                     gamma, bc[0], bc[1], bc[2], bc[3], p_exit, ref);
   return hipGetLastError();
 }
 

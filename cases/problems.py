@@ -62,21 +62,28 @@ def box_problem(n=32, seed=1, Cs=0.148, noise=1e-4, shape=None):
                 params=box_params(L, Cs=Cs))
 
 
-def jet_grid(nx, nr, nth):
-    return mesh.jet_axial(nx), mesh.jet_radial(nr), mesh.azimuth(nth)
+def jet_grid(nx, nr, nth, axis_node=False):
+    """1-D maps of the jet mesh; axis_node puts the radial row j = 0 on the
+    axis (r = 0) instead of at r = 0.005 D."""
+    R = mesh.jet_radial(nr, rmin=0.0) if axis_node else mesh.jet_radial(nr)
+    return mesh.jet_axial(nx), R, mesh.azimuth(nth)
 
 
 def jet_problem(nx, nr, nth, seed=2, coef=None, noise=1e-3 * flow.JET_UJ,
-                with_xyz=True, device="cpu", thermo_noise=0.0):
-    """Cylindrical jet mesh with the Mach-1.4 parallel-jet state."""
-    X, R, TH = jet_grid(nx, nr, nth)
+                with_xyz=True, device="cpu", thermo_noise=0.0, axis_node=False):
+    """Cylindrical jet mesh with the Mach-1.4 parallel-jet state.  axis_node:
+    mesh nodes on the axis with the centerline condition of the paper."""
+    X, R, TH = jet_grid(nx, nr, nth, axis_node)
     xyz = mesh.cylindrical_coords(X, R, TH, device=device) if with_xyz else None
     Q = flow.jet_state(X, R, TH, seed=seed, coef=coef, noise=noise, device=device,
                        thermo_noise=thermo_noise)
     inflow = flow.jet_inflow(R, TH, seed=seed, coef=coef, noise=noise, device=device,
                              thermo_noise=thermo_noise)
-    return dict(name=f"jet{nx}x{nr}x{nth}", xyz=xyz, Q=Q, inflow=inflow,
-                params=jet_params(), grid=(X, R, TH))
+    prm = jet_params()
+    if axis_node:
+        prm["bc"] = ("inflow", "outflow", "axis_node", "farfield", "periodic", "periodic")
+    return dict(name=f"jet{nx}x{nr}x{nth}" + ("_axisnode" if axis_node else ""), xyz=xyz, Q=Q,
+                inflow=inflow, params=prm, grid=(X, R, TH))
 
 
 def seeded_field(shape, seed, field, kind="gaussian", device="cpu"):

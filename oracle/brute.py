@@ -96,6 +96,10 @@ class Brute:
                         i, j, k = p
                         src = (i, m - 1, (k + self.n[2] // 2) % self.n[2])
                         self.X[p] = list(self.X[src])
+                    elif kind == "axis_node":          # mirror through the axis node
+                        i, j, k = p
+                        src = (i, m, (k + self.n[2] // 2) % self.n[2])
+                        self.X[p] = list(self.X[src])
                     else:
                         b0 = self.X[self._shift(p, d, m)]
                         b1 = self.X[self._shift(p, d, m + 1)]
@@ -166,6 +170,13 @@ class Brute:
             for j in range(nr):
                 for i in range(nx):
                     S[(i, j, k)] = [float(Q[c, k, j, i]) for c in range(5)]
+        axis_node = bc[2] == "axis_node"
+        if axis_node:
+            # centerline: mean over the azimuth of the row j = 1, for every k
+            for i in range(nx):
+                mean = [sum(S[(i, 1, k)][c] for k in range(nth)) / nth for c in range(5)]
+                for k in range(nth):
+                    S[(i, 0, k)] = list(mean)
         for d in range(3):
             nd = self.n[d]
             # low side
@@ -177,10 +188,14 @@ class Brute:
                     elif kind == "axis":
                         i, j, k = p
                         S[p] = list(S[(i, m - 1, (k + nth // 2) % nth)])
+                    elif kind == "axis_node":
+                        i, j, k = p
+                        S[p] = list(S[(i, m, (k + nth // 2) % nth)])
                     elif kind == "inflow":
                         e_pt = self._shift(p, d, m)
                         i, j, k = e_pt
-                        Sx = self.metric(e_pt)[0][0]
+                        n_pt = (i, 1, k) if axis_node and j == 0 else e_pt
+                        Sx = self.metric(n_pt)[0][0]
                         mag = math.sqrt(_dot(Sx, Sx))
                         n = [-c / mag for c in Sx]
                         t = [float(self.inflow[c][k][j]) for c in range(5)]
@@ -200,7 +215,8 @@ class Brute:
                         S[p] = list(S[self._shift(p, d, -nd)])
                     elif kind == "outflow":
                         e = self.prim(S[e_pt])
-                        Sx = self.metric(e_pt)[0][0]
+                        n_pt = (e_pt[0], 1, e_pt[2]) if axis_node and e_pt[1] == 0 else e_pt
+                        Sx = self.metric(n_pt)[0][0]
                         mag = math.sqrt(_dot(Sx, Sx))
                         n = [c / mag for c in Sx]
                         ae = math.sqrt(gam * e[4] / e[0])
@@ -317,10 +333,15 @@ class Brute:
         """Numerical flux at the face between L and L + e_d."""
         prm = self.prm
         R = self._shift(L, d, 1)
-        GL, GR = self.point_flux(S, L, d), self.point_flux(S, R, d)
+        axis_face = prm["bc"][2] == "axis_node" and d == 1 and L[1] == 0
+        GL = [0.0] * 5 if axis_face else self.point_flux(S, L, d)
+        GR = self.point_flux(S, R, d)
         e2 = prm["k2"] * max(self.sensor(S, L, d), self.sensor(S, R, d))
         e4 = max(0.0, prm["k4"] - e2)
-        lam = 0.5 * (self.lam_bar(S, L, d) + self.lam_bar(S, R, d))
+        if axis_face:     # the axis point has V = 0: lambda_bar of the j = 1 point
+            lam = self.lam_bar(S, R, d)
+        else:
+            lam = 0.5 * (self.lam_bar(S, L, d) + self.lam_bar(S, R, d))
         Vf = 0.5 * (self.metric(L)[1] + self.metric(R)[1])
         Wm = self.W(S, self._shift(L, d, -1))
         WL, WR = self.W(S, L), self.W(S, R)
@@ -329,8 +350,11 @@ class Brute:
                    (L[d] == self.n[d] - 1 and prm["bc"][2 * d + 1] in ("inflow", "outflow", "farfield"))
         out = []
         for c in range(5):
-            dis = 0.0 if physical else lam * (e2 * (WR[c] - WL[c])
-                                              - e4 * (Wp[c] - 3.0 * WR[c] + 3.0 * WL[c] - Wm[c]))
+            if axis_face:   # (Delta w)_{-1/2} = -(Delta w)_{1/2} at the centerline
+                d4 = Wp[c] - 4.0 * WR[c] + 3.0 * WL[c]
+            else:
+                d4 = Wp[c] - 3.0 * WR[c] + 3.0 * WL[c] - Wm[c]
+            dis = 0.0 if physical else lam * (e2 * (WR[c] - WL[c]) - e4 * d4)
             out.append(0.5 * (GL[c] + GR[c]) - Vf * dis)
         return out
 
@@ -343,6 +367,9 @@ class Brute:
             for j in range(nr):
                 for i in range(nx):
                     p = (i, j, k)
+                    if j == 0 and self.prm["bc"][2] == "axis_node":
+                        R[p] = [0.0] * 5          # the axis row is not advanced
+                        continue
                     acc = [0.0] * 5
                     for d in range(3):
                         Fp = self.face(S, p, d)

@@ -60,6 +60,22 @@ also listed in the design notes):
       unit normal.
   R24 branch ties: q/a >= 1 exit copy, q/a <= -1 outside state, q >= 0
       subsonic exit.
+  Centerline through mesh nodes (eta- kind "axis_node", subsection
+  "Centerline Boundary Condition"; the mesh has its j = 0 points on the
+  axis):
+  C1  before every residual the axis row takes the azimuthal mean of the
+      conserved variables of the row j = 1 (extrapolated and averaged); it
+      is not advanced by the scheme (R = 0 there);
+  C2  ghosts across the axis are the mirror points (i, m, k + nth/2);
+  C3  the eta point flux vanishes at the axis (S^eta = 0 there; the
+      viscous terms, singular at V = 0, are not evaluated);
+  C4  the dissipation at the axis face uses lambda_bar of the j = 1 point
+      (the axis point has V = 0) and the modified fourth difference of the
+      centerline subsection, (Delta w)_{-1/2} = -(Delta w)_{1/2}, i.e.
+      W_{2} - 4 W_{1} + 3 W_{0} in place of W_{2} - 3 W_{1} + 3 W_{0} - W_{-1};
+  C5  boundary normals of axis points (entrance, exit) are those of the
+      j = 1 point (S^xi vanishes on the axis);
+  C6  the time step maximum runs over j >= 1.
 
 The code is dtype-generic: complex128 arrays give complex-step derivatives
 (abs, max and branch tests act on real parts).
@@ -134,6 +150,8 @@ def pad_coords(xyz, prm):
             elif lo_kind == "axis":
                 # eta direction: the other (zeta) axis of L is axis 1
                 L[..., lo] = np.roll(L[..., g + m - 1], -(n[2] // 2), axis=1)
+            elif lo_kind == "axis_node":               # mirror through the axis node (C2)
+                L[..., lo] = np.roll(L[..., g + m], -(n[2] // 2), axis=1)
             else:
                 L[..., lo] = L[..., g] + m * (L[..., g] - L[..., g + 1])
             if hi_kind == "periodic":
@@ -290,10 +308,17 @@ def fill_ghosts(Qp, geo, prm, inflow=None):
     nth, nr, nx = nthp - 2 * g, nrp - 2 * g, nxp - 2 * g
     n = (nx, nr, nth)
 
+    axis_node = bc[2] == "axis_node"
+    if axis_node:                                   # (C1) axis row = mean of row j = 1
+        ring = Qp[:, g:g + nth, g + 1, g:g + nx]
+        Qp[:, g:g + nth, g, g:g + nx] = np.mean(ring, axis=1, keepdims=True)
     for d in range(3):
         lo_kind, hi_kind = bc[2 * d], bc[2 * d + 1]
         L = _fill_region(Qp, d, g)                  # (5, a, b, n_d + 2g)
         Sd = _fill_region(S[d], d, g)               # (3, a, b, n_d + 2g)
+        if axis_node and d == 0:                    # (C5) normals of the row j = 1
+            Sd = Sd.copy()
+            Sd[:, :, 0, :] = Sd[:, :, 1, :]
         nd = n[d]
         # periodic wraps
         if lo_kind == "periodic":
@@ -306,6 +331,9 @@ def fill_ghosts(Qp, geo, prm, inflow=None):
         if lo_kind == "axis":
             for m in range(1, g + 1):
                 L[..., g - m] = np.roll(L[..., g + m - 1], -(n[2] // 2), axis=1)
+        if lo_kind == "axis_node":                  # (C2)
+            for m in range(1, g + 1):
+                L[..., g - m] = np.roll(L[..., g + m], -(n[2] // 2), axis=1)
 
         if lo_kind == "inflow":
             Qe = L[..., g]
@@ -479,6 +507,9 @@ def point_terms(Qp, geo, prm):
         nu.append(rabs(pp - 2.0 * p1 + pm) / (pp + 2.0 * p1 + pm))
     out.update(lam=lam, lam_bar=lam_bar, nu=nu, V=V,
                W=np.stack([Qp[0], Qp[1], Qp[2], Qp[3], Qp[4] + p]))
+    if prm["bc"][2] == "axis_node":
+        # (C3) region one starts at j = -1, so the axis row is index 1
+        out["G"][1][..., 1, :] = 0.0
     return out
 
 
@@ -497,7 +528,14 @@ def face_fluxes(pt, d, prm):
     lam_f = 0.5 * (lb[..., :-1] + lb[..., 1:])
     V_f = 0.5 * (V[..., :-1] + V[..., 1:])
     Wm, WL, WR, Wp = W[..., :-3], W[..., 1:-2], W[..., 2:-1], W[..., 3:]
-    dis = lam_f * (eps2 * (WR - WL) - eps4 * (Wp - 3.0 * WR + 3.0 * WL - Wm))
+    d4 = Wp - 3.0 * WR + 3.0 * WL - Wm
+    if d == 1 and prm["bc"][2] == "axis_node":
+        # (C4) the axis face is face index 1 (L = 0, R = 1)
+        lam_f = lam_f.copy()
+        lam_f[..., 1] = lb[..., 2]
+        d4 = d4.copy()
+        d4[..., 1] = Wp[..., 1] - 4.0 * WR[..., 1] + 3.0 * WL[..., 1]
+    dis = lam_f * (eps2 * (WR - WL) - eps4 * d4)
     lo_kind, hi_kind = prm["bc"][2 * d], prm["bc"][2 * d + 1]
     if lo_kind in PHYSICAL_FACE_KINDS:     # R15
         dis[..., 0] = 0.0
@@ -509,15 +547,18 @@ def face_fluxes(pt, d, prm):
 def residual(Qp, geo, prm):
     """R = RHS / V on the interior, for a padded state whose ghosts are
     filled; dQ/dt = -R (eq. spatial_discret with unit index spacing)."""
-    pt = point_terms(Qp, geo, prm)
-    g = NG
-    _, nthp, nrp, nxp = Qp.shape
-    rhs = 0.0
-    for d in range(3):
-        F = face_fluxes(pt, d, prm)
-        diff = F[..., 1:] - F[..., :-1]
-        rhs = rhs + np.moveaxis(diff, -1, diff.ndim - 1 - d)
-    return rhs / interior(geo["V"])
+    axis_node = prm["bc"][2] == "axis_node"
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        pt = point_terms(Qp, geo, prm)
+        rhs = 0.0
+        for d in range(3):
+            F = face_fluxes(pt, d, prm)
+            diff = F[..., 1:] - F[..., :-1]
+            rhs = rhs + np.moveaxis(diff, -1, diff.ndim - 1 - d)
+        R = rhs / interior(geo["V"])
+    if axis_node:
+        R[:, :, 0, :] = 0.0                          # (C1) the axis row is not advanced
+    return R
 
 
 def lambda_sum(Qp, geo, prm):
@@ -529,9 +570,13 @@ def lambda_sum(Qp, geo, prm):
     rho, u, v, w, p = primitives(Q, gamma)
     a = np.sqrt(gamma * p / rho)
     tot = 0.0
-    for d in range(3):
-        Uc = S[d, 0] * u + S[d, 1] * v + S[d, 2] * w
-        tot = tot + (rabs(Uc) + a * np.sqrt(S[d, 0] ** 2 + S[d, 1] ** 2 + S[d, 2] ** 2)) / rabs(V)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for d in range(3):
+            Uc = S[d, 0] * u + S[d, 1] * v + S[d, 2] * w
+            tot = tot + (rabs(Uc) + a * np.sqrt(S[d, 0] ** 2 + S[d, 1] ** 2 + S[d, 2] ** 2)) / rabs(V)
+    if prm["bc"][2] == "axis_node":
+        tot = tot.copy()
+        tot[:, 0, :] = 0.0                           # (C6) the axis row has V = 0
     return tot
 
 

@@ -74,7 +74,22 @@ enum les_bc {
                              (i, m, k + nth/2); needs even nth, zeta periodic */
   LES_BC_INFLOW = 2,      /* xi-: entrance; target primitives from les_set_inflow */
   LES_BC_OUTFLOW = 3,     /* xi+: exit with back pressure p_exit */
-  LES_BC_FARFIELD = 4     /* eta+: Riemann invariants with ref_prim */
+  LES_BC_FARFIELD = 4,    /* eta+: Riemann invariants with ref_prim */
+  LES_BC_AXIS_NODE = 5    /* eta-: the row j = 0 lies on the axis (subsection
+                             "Centerline Boundary Condition"): before every
+                             residual it takes the azimuthal mean of the
+                             conserved variables of row j = 1 and R = 0 there;
+                             ghosts are the mirror points (i, m, k + nth/2);
+                             the eta point flux vanishes on the axis; the axis
+                             face uses lambda_bar of row 1 and the three-point
+                             fourth difference W2 - 4 W1 + 3 W0; entrance and
+                             exit normals of axis points are those of row 1;
+                             the CFL maximum skips the axis.  The axis row of
+                             the caller's state is derived data: the ghost fill
+                             of les_residual / les_rk5_step writes the mean into
+                             it, and les_rk5_step returns it as the mean of the
+                             returned state's row 1.  Needs even nth; the
+                             adjoint entry points return LES_EUNSUPPORTED. */
 };
 
 /* Subgrid-scale eddy viscosity (subsection "Subgrid Scale Modeling"), in

@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("LESJET_LIB") or os.path.join(
 LES_OK, LES_EINVAL, LES_ENOMEM, LES_EHIP, LES_ENONFINITE, LES_ESTATE, LES_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 LES_FP64, LES_FP32_STORAGE = 0, 1
-BC = {"periodic": 0, "axis": 1, "inflow": 2, "outflow": 3, "farfield": 4}
+BC = {"periodic": 0, "axis": 1, "inflow": 2, "outflow": 3, "farfield": 4, "axis_node": 5}
 SGS = {0: 0, 1: 1, 2: 2, "none": 0, "smagorinsky": 1, "vreman": 2}
 STATUS = {0: "LES_OK", -1: "LES_EINVAL", -2: "LES_ENOMEM", -3: "LES_EHIP",
           -4: "LES_ENONFINITE", -5: "LES_ESTATE", -6: "LES_EUNSUPPORTED"}

@@ -89,7 +89,9 @@ static int validate(const les_params* p, std::string& why) {
   if (p->nx < 5 || p->nr < 5 || p->nth < 5) { why = "each of nx, nr, nth must be >= 5"; return LES_EINVAL; }
   const int* b = p->bc;
   for (int f = 0; f < 6; ++f)
-    if (b[f] < LES_BC_PERIODIC || b[f] > LES_BC_FARFIELD) { why = "unknown boundary kind"; return LES_EINVAL; }
+    if (b[f] < LES_BC_PERIODIC || b[f] > LES_BC_AXIS_NODE) { why = "unknown boundary kind"; return LES_EINVAL; }
+  for (int f = 0; f < 6; ++f)
+    if (b[f] == LES_BC_AXIS_NODE && f != 2) { why = "axis_node is an eta- condition"; return LES_EINVAL; }
   for (int d = 0; d < 3; ++d)
     if ((b[2 * d] == LES_BC_PERIODIC) != (b[2 * d + 1] == LES_BC_PERIODIC)) {
       why = "a periodic direction must be periodic on both faces";
@@ -97,10 +99,16 @@ static int validate(const les_params* p, std::string& why) {
     }
   if (!(b[0] == LES_BC_PERIODIC || b[0] == LES_BC_INFLOW)) { why = "xi- must be periodic or inflow"; return LES_EINVAL; }
   if (!(b[1] == LES_BC_PERIODIC || b[1] == LES_BC_OUTFLOW)) { why = "xi+ must be periodic or outflow"; return LES_EINVAL; }
-  if (!(b[2] == LES_BC_PERIODIC || b[2] == LES_BC_AXIS)) { why = "eta- must be periodic or axis"; return LES_EINVAL; }
+  if (!(b[2] == LES_BC_PERIODIC || b[2] == LES_BC_AXIS || b[2] == LES_BC_AXIS_NODE)) {
+    why = "eta- must be periodic, axis or axis_node";
+    return LES_EINVAL;
+  }
   if (!(b[3] == LES_BC_PERIODIC || b[3] == LES_BC_FARFIELD)) { why = "eta+ must be periodic or far field"; return LES_EINVAL; }
   if (b[4] != LES_BC_PERIODIC || b[5] != LES_BC_PERIODIC) { why = "zeta must be periodic"; return LES_EINVAL; }
-  if (b[2] == LES_BC_AXIS && (p->nth % 2) != 0) { why = "the axis condition needs an even nth"; return LES_EINVAL; }
+  if ((b[2] == LES_BC_AXIS || b[2] == LES_BC_AXIS_NODE) && (p->nth % 2) != 0) {
+    why = "the axis conditions need an even nth";
+    return LES_EINVAL;
+  }
   if (!(std::isfinite(p->gamma) && p->gamma > 1.0)) { why = "gamma must be > 1"; return LES_EINVAL; }
   if (!finite_pos(p->Pr) || !finite_pos(p->Pr_sgs)) { why = "Prandtl numbers must be > 0"; return LES_EINVAL; }
   if (!(std::isfinite(p->visc_coef) && p->visc_coef >= 0.0)) { why = "visc_coef must be >= 0"; return LES_EINVAL; }
@@ -165,6 +173,7 @@ static Phys<T> make_phys(const les_params* p) {
   ph.sgs_coef = ph.sgs ? (T)(c / p->visc_coef) : T(0);
   ph.k2 = (T)p->k2;
   ph.k4 = (T)p->k4;
+  ph.axis_node = p->bc[2] == LES_BC_AXIS_NODE;
   for (int d = 0; d < 3; ++d)
     for (int s = 0; s < 2; ++s) {
       const int b = p->bc[2 * d + s];
@@ -461,6 +470,9 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
     }
     cur = src;
   }
+  // centerline through the nodes: the axis row is not advanced; on return it
+  // holds the azimuthal mean of the returned state's row j = 1
+  if (e == hipSuccess && c->p.bc[2] == LES_BC_AXIS_NODE) e = launch_centerline<double>(Qn, c->g, s);
   if (e != hipSuccess) return hip_fail(c, e, "rk5 kernels");
   int flag = 0;
   HIP_TRY(c, hipMemcpyAsync(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -523,6 +535,8 @@ static int adjoint_ready(les_ctx* c) {
   if (r != LES_OK) return r;
   if (c->p.precision != LES_FP64)
     return fail(c, LES_EUNSUPPORTED, "the adjoint is available for the FP64 precision only");
+  if (c->p.bc[2] == LES_BC_AXIS_NODE)
+    return fail(c, LES_EUNSUPPORTED, "the adjoint does not cover the axis_node centerline");
   return LES_OK;
 }
 

@@ -33,7 +33,9 @@ struct CGrid {
 };
 
 // Boundary kinds (values of the public enum les_bc).
-enum : int { BC_PERIODIC = 0, BC_AXIS = 1, BC_INFLOW = 2, BC_OUTFLOW = 3, BC_FARFIELD = 4 };
+enum : int {
+  BC_PERIODIC = 0, BC_AXIS = 1, BC_INFLOW = 2, BC_OUTFLOW = 3, BC_FARFIELD = 4, BC_AXIS_NODE = 5
+};
 
 // Constants of the discretisation in compute precision T.
 template <typename T>
@@ -47,6 +49,7 @@ struct Phys {
   T k2, k4;
   int viscous;            // Cv != 0
   int sgs;                // 0 none, 1 Smagorinsky, 2 Vreman
+  int axis_node;          // eta- is a centerline through the mesh nodes j = 0
   int phys_face[3][2];    // face -1/2 / n-1/2 along d is a physical boundary
 };
 

@@ -51,6 +51,10 @@ __global__ void k_coord_ghost(double* __restrict__ C, CGrid g, int dir, int lo_k
         // dir == 1: the point across the axis, (i, m-1, k + nth/2)
         const int kk = (b + g.nth / 2) % g.nth;
         lo = X[g.at(a, m - 1, kk)];
+      } else if (lo_kind == BC_AXIS_NODE) {
+        // dir == 1: the mirror point through the axis node, (i, m, k + nth/2)
+        const int kk = (b + g.nth / 2) % g.nth;
+        lo = X[g.at(a, m, kk)];
       } else {
         lo = X[idx(0)] + m * (X[idx(0)] - X[idx(1)]);
       }

@@ -44,12 +44,15 @@ __device__ __forceinline__ void unit_normal(const T* M, int vs, int o, int d, do
 // filled in parallel.
 
 // State of (i, j, k), i padded, j and k interior, after the xi sweep.
+// With a centerline through the nodes j = 0 (axis_node), the boundary
+// normals of axis points are those of row j = 1 (S^xi vanishes on the axis).
 template <typename T>
 __device__ __forceinline__ void xi_value(const T* __restrict__ Q, const Grid& g,
                                          const T* __restrict__ M,
                                          const double* __restrict__ inflow, double gamma,
-                                         int lo_kind, int hi_kind, double p_exit, int i, int j,
-                                         int k, T q[5]) {
+                                         int lo_kind, int hi_kind, double p_exit, int axis_node,
+                                         int i, int j, int k, T q[5]) {
+  const int jn = axis_node && j == 0 ? 1 : j;
   if (i >= 0 && i < g.nx) {
     load5(Q, g.vs, g.at(i, j, k), q);
   } else if (i < 0) {
@@ -60,7 +63,7 @@ __device__ __forceinline__ void xi_value(const T* __restrict__ Q, const Grid& g,
       T qe[5];
       load5(Q, g.vs, oe, qe);
       double n[3];
-      unit_normal(M, g.vs, oe, 0, -1.0, n);
+      unit_normal(M, g.vs, g.at(0, jn, k), 0, -1.0, n);
       BPrim<T> tg;
       const long long sp = (long long)g.nth * g.nr, it = (long long)k * g.nr + j;
       tg.rho = (T)inflow[0 * sp + it];
@@ -78,7 +81,7 @@ __device__ __forceinline__ void xi_value(const T* __restrict__ Q, const Grid& g,
       T qe[5];
       load5(Q, g.vs, oe, qe);
       double n[3];
-      unit_normal(M, g.vs, oe, 0, 1.0, n);
+      unit_normal(M, g.vs, g.at(g.nx - 1, jn, k), 0, 1.0, n);
       bc_outflow(qe, n, gamma, p_exit, q);
     }
   }
@@ -115,21 +118,24 @@ __global__ void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
   const int og = g.at(i, j, k);
   // zeta sweep (periodic): the wrapped point
   int kw = k < 0 ? k + g.nth : (k >= g.nth ? k - g.nth : k);
+  const int an = elo == BC_AXIS_NODE;
   // eta sweep
   T q[5];
   if (j >= 0 && j < g.nr) {
-    xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, j, kw, q);
+    xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, an, i, j, kw, q);
   } else if (j < 0) {
     if (elo == BC_PERIODIC)
-      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, j + g.nr, kw, q);
-    else                                         // across the axis
-      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, -1 - j, (kw + g.nth / 2) % g.nth, q);
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, an, i, j + g.nr, kw, q);
+    else if (elo == BC_AXIS)                     // across the axis
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, an, i, -1 - j, (kw + g.nth / 2) % g.nth, q);
+    else                                         // mirror through the axis node
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, an, i, -j, (kw + g.nth / 2) % g.nth, q);
   } else {
     if (ehi == BC_PERIODIC) {
-      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, j - g.nr, kw, q);
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, an, i, j - g.nr, kw, q);
     } else {                                     // far field from the state at (i, nr-1)
       T qe[5];
-      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, i, g.nr - 1, kw, qe);
+      xi_value(Q, g, M, inflow, gamma, xlo, xhi, p_exit, an, i, g.nr - 1, kw, qe);
       double n[3];
       unit_normal(M, g.vs, g.at(i, g.nr - 1, kw), 1, 1.0, n);
       bc_farfield(qe, ref, n, gamma, q);
@@ -138,10 +144,45 @@ __global__ void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
   store5(Q, g.vs, og, q);
 }
 
+// Centerline through the nodes j = 0: the axis row takes the azimuthal mean
+// of the conserved variables of row j = 1 (one block per i, a fixed-order
+// FP64 tree over k, so the value is the same for every k and reproducible).
+constexpr int CL_BS = 256;
+
+template <typename T>
+__global__ void k_centerline(T* __restrict__ Q, Grid g) {
+  __shared__ double red[5][CL_BS];
+  const int i = blockIdx.x;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < g.nth; k += CL_BS) {
+    const int o = g.at(i, 1, k);
+    for (int c = 0; c < 5; ++c) acc[c] += (double)Q[(long long)c * g.vs + o];
+  }
+  for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = CL_BS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 5; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < g.nth; k += CL_BS) {
+    const int o = g.at(i, 0, k);
+    for (int c = 0; c < 5; ++c) Q[(long long)c * g.vs + o] = (T)(red[c][0] / g.nth);
+  }
+}
+
+template <typename T>
+hipError_t launch_centerline(T* Q, const Grid& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_centerline<T>, dim3(g.nx), dim3(CL_BS), 0, s, Q, g);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
                          const Phys<T>& ph, const int bc[6], const double ref_prim[5],
                          double p_exit, hipStream_t s) {
+  if (bc[2] == BC_AXIS_NODE)
+    hipLaunchKernelGGL(k_centerline<T>, dim3(g.nx), dim3(CL_BS), 0, s, Q, g);
   const double gamma = (double)ph.gamma;
   BPrim<T> ref;
   ref.rho = (T)ref_prim[0]; ref.u = (T)ref_prim[1]; ref.v = (T)ref_prim[2];
@@ -153,6 +194,7 @@ hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
   return hipGetLastError();
 }
 
+template hipError_t launch_centerline<double>(double*, const Grid&, hipStream_t);
 template hipError_t launch_ghosts<double>(double*, const Grid&, const double*, const double*,
                                           const Phys<double>&, const int*, const double*, double,
                                           hipStream_t);

@@ -13,6 +13,10 @@ template <typename T>
 hipError_t launch_metrics(const double* C, const CGrid& cg, T* M, const Grid& g, double* M64,
                           hipStream_t s);
 
+// Axis row j = 0 := azimuthal mean of row j = 1 (centerline through the nodes).
+template <typename T>
+hipError_t launch_centerline(T* Q, const Grid& g, hipStream_t s);
+
 template <typename T>
 hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow, const Phys<T>& ph,
                          const int bc[6], const double ref_prim[5], double p_exit, hipStream_t s);

@@ -103,7 +103,9 @@ struct TileMap {
 // FP32 to 128 for more waves costs spills and measured slower).
 template <typename T> struct FusedOcc { static constexpr int waves = 2; };
 
-template <typename T, int EPI>
+// AXIS: the eta- face is a centerline through mesh nodes (row j = 0 on the
+// axis); a separate instance so that the common case carries none of it.
+template <typename T, int EPI, bool AXIS>
 __global__ void __launch_bounds__(Tile<T>::X * Tile<T>::Y, FusedOcc<T>::waves)
 k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, int kc,
         TileMap tm, T* out, const double* Q0, double* Q64, double alpha,
@@ -151,6 +153,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
   const bool phys_im = i == 0 && ph.phys_face[0][0];
   const bool phys_ip = i == g.nx - 1 && ph.phys_face[0][1];
   const bool phys_jm = j == 0 && ph.phys_face[1][0];
+  const bool axis_row = AXIS && j == 0;      // centerline row (not advanced)
+  const bool axis_face = AXIS && j == 1;     // face j - 1/2 is the axis face
   const bool phys_jp = j == g.nr - 1 && ph.phys_face[1][1];
 
   // ---- rolling column state ------------------------------------------------
@@ -239,6 +243,12 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
       for (int c = 0; c < 3; ++c) in.S[d][c] = met[3 * d + c];
     in.V = met[9];
     point_quantities(in, ph, po);
+    if (AXIS && axis_row) {
+      // centerline through the nodes: S^eta = 0 on the axis, so the eta
+      // point flux vanishes (its viscous part, singular at V = 0, is not used)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) po.G[1][c] = T(0);
+    }
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       sX[c][ty][tx] = po.G[0][c];
@@ -286,12 +296,18 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
         }
         {
           T GA[5], GB[5];
-          wload(ty - 1, tx + 1, Wm); wload(ty, tx + 1, Wl); wload(ty + 1, tx + 1, Wr);
+          // axis face: lambda_bar of row 1 and the three-point fourth
+          // difference W(2) - 4 W(1) + 3 W(0), i.e. the standard formula with
+          // W(-1) replaced by W(1); done by choosing the rows read
+          const int rm = AXIS && axis_face ? ty + 1 : ty - 1;
+          const int rl = AXIS && axis_face ? ty : ty - 1;
+          wload(rm, tx + 1, Wm); wload(ty, tx + 1, Wl); wload(ty + 1, tx + 1, Wr);
           wload(ty + 2, tx + 1, Wp);
 #pragma unroll
           for (int c = 0; c < 5; ++c) { GA[c] = sE[c][ty - 1][tx]; GB[c] = sE[c][ty][tx]; }
-          face_flux(GA, GB, sE[5][ty - 1][tx], sE[5][ty][tx], sE[6][ty - 1][tx], sE[6][ty][tx],
-                    sE[7][ty - 1][tx], sE[7][ty][tx], Wm, Wl, Wr, Wp, phys_jm, ph, Fm);
+          face_flux(GA, GB, sE[5][rl][tx], sE[5][ty][tx],
+                    sE[6][ty - 1][tx], sE[6][ty][tx], sE[7][ty - 1][tx], sE[7][ty][tx],
+                    Wm, Wl, Wr, Wp, phys_jm, ph, Fm);
           wload(ty + 3, tx + 1, Wm);
 #pragma unroll
           for (int c = 0; c < 5; ++c) GA[c] = sE[c][ty + 1][tx];
@@ -314,7 +330,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
         const T iV = trcp(Vz);
         T R[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) R[c] = (acc[c] + Fk[c]) * iV;
+        for (int c = 0; c < 5; ++c) R[c] = AXIS && axis_row ? T(0) : (acc[c] + Fk[c]) * iV;
         if (EPI == EPI_R) {
 #pragma unroll
           for (int c = 0; c < 5; ++c) out[(long long)c * g.vs + o] = R[c];
@@ -335,7 +351,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
 #pragma unroll
               for (int c = 0; c < 3; ++c) S[d][c] = (double)M[(long long)(3 * d + c) * g.vs + o];
             const double x = lambda_sum(qn, S, (double)Vz, ph64);
-            if (x != x || x > lmax) lmax = x;
+            if (!(AXIS && axis_row) && (x != x || x > lmax)) lmax = x;
           }
         }
       }
@@ -426,15 +442,19 @@ hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph
   tm.per_xcd = (int)((ntiles + NXCD - 1) / NXCD);
   const dim3 grid((unsigned)(tm.per_xcd * NXCD));
   const dim3 block(Tile<T>::X, Tile<T>::Y, 1);
-  if (epi == EPI_R)
-    hipLaunchKernelGGL((k_fused<T, EPI_R>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0, Q64,
-                       alpha, dt, ph64, maxbits);
-  else if (epi == EPI_RK)
-    hipLaunchKernelGGL((k_fused<T, EPI_RK>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0, Q64,
-                       alpha, dt, ph64, maxbits);
-  else
-    hipLaunchKernelGGL((k_fused<T, EPI_RK_LAST>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0,
-                       Q64, alpha, dt, ph64, maxbits);
+#define LESJET_FUSED(E, A)                                                                   \
+  hipLaunchKernelGGL((k_fused<T, E, A>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0, Q64, \
+                     alpha, dt, ph64, maxbits)
+  if (ph.axis_node) {
+    if (epi == EPI_R) LESJET_FUSED(EPI_R, true);
+    else if (epi == EPI_RK) LESJET_FUSED(EPI_RK, true);
+    else LESJET_FUSED(EPI_RK_LAST, true);
+  } else {
+    if (epi == EPI_R) LESJET_FUSED(EPI_R, false);
+    else if (epi == EPI_RK) LESJET_FUSED(EPI_RK, false);
+    else LESJET_FUSED(EPI_RK_LAST, false);
+  }
+#undef LESJET_FUSED
   return hipGetLastError();
 }
 

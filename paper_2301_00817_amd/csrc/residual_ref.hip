@@ -46,6 +46,8 @@ __global__ void k_point_pass(const T* __restrict__ Q, const T* __restrict__ M, G
   in.V = M[9LL * g.vs + o];
   PointOut<T> out;
   point_quantities(in, ph, out);
+  if (ph.axis_node && j == 0)          // centerline through the nodes: no eta point flux
+    for (int c = 0; c < 5; ++c) out.G[1][c] = T(0);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -88,14 +90,18 @@ __global__ void k_face_pass(const T* __restrict__ Q, const T* __restrict__ M, Gr
     T Fm[5], Fp[5];
     const bool phys_m = pos[d] == 0 && ph.phys_face[d][0];
     const bool phys_p = pos[d] == nn[d] - 1 && ph.phys_face[d][1];
-    face_flux(G[0], G[1], lb[0], lb[1], nu[0], nu[1], V[0], V[1], W[0], W[1], W[2], W[3], phys_m,
-              ph, Fm);
+    // axis face (centerline through the nodes): lambda_bar of row 1 and the
+    // three-point fourth difference (W(-1) replaced by W(1))
+    const bool axis_face = ph.axis_node && d == 1 && j == 1;
+    face_flux(G[0], G[1], axis_face ? lb[1] : lb[0], lb[1], nu[0], nu[1], V[0], V[1],
+              axis_face ? W[2] : W[0], W[1], W[2], W[3], phys_m, ph, Fm);
     face_flux(G[1], G[2], lb[1], lb[2], nu[1], nu[2], V[1], V[2], W[1], W[2], W[3], W[4], phys_p,
               ph, Fp);
     for (int c = 0; c < 5; ++c) rhs[c] += Fp[c] - Fm[c];
   }
   const T iV = trcp(M[9LL * g.vs + o]);
-  for (int c = 0; c < 5; ++c) R[(long long)c * g.vs + o] = rhs[c] * iV;
+  const bool axis_row = ph.axis_node && j == 0;   // not advanced
+  for (int c = 0; c < 5; ++c) R[(long long)c * g.vs + o] = axis_row ? T(0) : rhs[c] * iV;
 }
 
 template <typename T>

@@ -21,6 +21,7 @@ __global__ void k_lambda_max(const TQ* __restrict__ Q, const TM* __restrict__ M,
     const int i = (int)(t % g.nx);
     const int j = (int)((t / g.nx) % g.nr);
     const int k = (int)(t / ((long long)g.nx * g.nr));
+    if (ph.axis_node && j == 0) continue;    // centerline row is not advanced
     const int o = g.at(i, j, k);
     double q[5], S[3][3];
     for (int c = 0; c < 5; ++c) q[c] = (double)Q[(long long)c * g.vs + o];

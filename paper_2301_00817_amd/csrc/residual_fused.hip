@@ -29,7 +29,7 @@
 namespace lesjet {
 
 // Tile shape per precision (threads along i and j of a ring-1 tile):
-// FP64 16 x 16 (LDS 59 KB, two blocks per CU), FP32 32 x 8 (LDS 30 KB, three
+// FP64 16 x 16 (LDS 79 KB, two blocks per CU), FP32 32 x 8 (LDS 40 KB, four
 // blocks per CU); both measured fastest among 64x8, 32x8 and 16x16 on the
 // jet meshes.
 template <typename T> struct Tile;
@@ -45,22 +45,37 @@ template <> struct Tile<float> {
   static constexpr int X = LESJET_TILE32_X, Y = LESJET_TILE32_Y, PER_CU = LESJET_TILE32_PER_CU;
 };
 #else
-template <> struct Tile<float> { static constexpr int X = 32, Y = 8, PER_CU = 3; };
+template <> struct Tile<float> { static constexpr int X = 32, Y = 8, PER_CU = 4; };
 #endif
 
 constexpr int NPQ = 8;                // G(5), lambda_bar, nu, V per direction
 
-// LDS buffers of the plane state: two where the LDS budget allows it (FP32),
-// one for FP64 (two blocks of 59 KB per CU leave no room for a second).
+// LDS buffers of the plane state: one (a second saves a barrier per plane,
+// but costs a block per CU in either precision).
 template <typename T> struct PlaneBuffers;
 #if defined(LESJET_DBUF32)
 template <> struct PlaneBuffers<float> { static constexpr int n = LESJET_DBUF32; };
 #else
-template <> struct PlaneBuffers<float> { static constexpr int n = 2; };
+template <> struct PlaneBuffers<float> { static constexpr int n = 1; };
 #endif
 template <> struct PlaneBuffers<double> { static constexpr int n = 1; };
 
 enum { EPI_R = 0, EPI_RK = 1, EPI_RK_LAST = 2 };
+
+// In-plane faces: each face evaluated once (by the column on its + side,
+// results exchanged through LDS, one more barrier) instead of once from each
+// side: fewer instructions and registers (FP64 no longer spills, FP32 fits
+// 128 VGPRs for four blocks per CU); measured 11-14 % faster in FP64 and,
+// with the four blocks, 5-6 % in FP32.
+template <typename T> struct FaceOnce;
+#ifndef LESJET_FACE_ONCE64
+#define LESJET_FACE_ONCE64 1
+#endif
+#ifndef LESJET_FACE_ONCE32
+#define LESJET_FACE_ONCE32 1
+#endif
+template <> struct FaceOnce<double> { static constexpr bool on = LESJET_FACE_ONCE64 != 0; };
+template <> struct FaceOnce<float> { static constexpr bool on = LESJET_FACE_ONCE32 != 0; };
 
 template <typename T>
 __device__ __forceinline__ void load_q(const T* __restrict__ Q, const Grid& g, int i, int j, int k,
@@ -99,9 +114,14 @@ struct TileMap {
   int per_xcd;          // ceil(gx gy gz / NXCD)
 };
 
-// Register budget: two waves per SIMD (FP64 uses all 256 VGPRs; constraining
-// FP32 to 128 for more waves costs spills and measured slower).
-template <typename T> struct FusedOcc { static constexpr int waves = 2; };
+// Register budget: FP64 two waves per SIMD (242 VGPRs), FP32 four (128).
+template <typename T> struct FusedOcc;
+template <> struct FusedOcc<double> { static constexpr int waves = 2; };
+#ifdef LESJET_OCC32
+template <> struct FusedOcc<float> { static constexpr int waves = LESJET_OCC32; };
+#else
+template <> struct FusedOcc<float> { static constexpr int waves = 4; };
+#endif
 
 // AXIS: the eta- face is a centerline through mesh nodes (row j = 0 on the
 // axis); a separate instance so that the common case carries none of it.
@@ -124,6 +144,10 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
   __shared__ T sPb[NB][5][FR_Y][FR_X];
   __shared__ T sX[NPQ][FB_Y][FB_X];
   __shared__ T sE[NPQ][FB_Y][FB_X];
+  constexpr bool ONCE = FaceOnce<T>::on;
+  // fluxes of the faces i - 1/2 (xi) and j - 1/2 (eta) of each column
+  __shared__ T sFx[ONCE ? 5 : 1][ONCE ? FB_Y : 1][ONCE ? FB_X : 1];
+  __shared__ T sFe[ONCE ? 5 : 1][ONCE ? FB_Y : 1][ONCE ? FB_X : 1];
   __shared__ double sRed[(FB_X * FB_Y + 63) / 64];
 
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -140,6 +164,9 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
   const int i = i0 - 1 + tx, j = j0 - 1 + ty;
   const bool col_ok = i >= -1 && i <= g.nx && j >= -1 && j <= g.nr;   // needed ring-1 column
   const bool interior = tx >= 1 && tx <= FT_X && ty >= 1 && ty <= FT_Y && i < g.nx && j < g.nr;
+  // columns that evaluate their xi face i - 1/2 / eta face j - 1/2
+  const bool xface = tx >= 1 && ty >= 1 && ty <= FT_Y && i <= g.nx && j < g.nr;
+  const bool eface = ty >= 1 && tx >= 1 && tx <= FT_X && j <= g.nr && i < g.nx;
 
   // ring-2 border point handled by this thread (if tid < NBORDER)
   const bool has_b = tid < NBORDER;
@@ -156,6 +183,9 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
   const bool axis_row = AXIS && j == 0;      // centerline row (not advanced)
   const bool axis_face = AXIS && j == 1;     // face j - 1/2 is the axis face
   const bool phys_jp = j == g.nr - 1 && ph.phys_face[1][1];
+  // the face i - 1/2 of column i = nx is the face nx - 1/2
+  const bool phys_xf = (i == 0 && ph.phys_face[0][0]) || (i == g.nx && ph.phys_face[0][1]);
+  const bool phys_ef = (j == 0 && ph.phys_face[1][0]) || (j == g.nr && ph.phys_face[1][1]);
 
   // ---- rolling column state ------------------------------------------------
   // The state and primitives of the current plane kk live in LDS once phase
@@ -265,19 +295,53 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     if (more && has_b) load_q(Qin, g, bi, bj, kk + 1, Bn);
     __syncthreads();
 
-    // (c) faces of the interior columns
+    // (c) faces
+    auto wload = [&](int yy, int xx, T w[5]) {      // W = Q with E replaced by E + p
+#pragma unroll
+      for (int c = 0; c < 4; ++c) w[c] = sQ[c][yy][xx];
+      w[4] = sQ[4][yy][xx] + sP[4][yy][xx];
+    };
+    if (ONCE && kk >= k0 && kk < k1) {
+      // in-plane faces of the output planes, one per column and direction
+      T Wm[5], Wl[5], Wr[5], Wp[5], F[5], GA[5], GB[5];
+      if (xface) {
+        wload(ty + 1, tx - 1, Wm); wload(ty + 1, tx, Wl); wload(ty + 1, tx + 1, Wr);
+        wload(ty + 1, tx + 2, Wp);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) { GA[c] = sX[c][ty][tx - 1]; GB[c] = sX[c][ty][tx]; }
+        face_flux(GA, GB, sX[5][ty][tx - 1], sX[5][ty][tx], sX[6][ty][tx - 1], sX[6][ty][tx],
+                  sX[7][ty][tx - 1], sX[7][ty][tx], Wm, Wl, Wr, Wp, phys_xf, ph, F);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sFx[c][ty][tx] = F[c];
+      }
+      if (eface) {
+        // axis face: lambda_bar of row 1 and the three-point fourth
+        // difference W(2) - 4 W(1) + 3 W(0), i.e. the standard formula with
+        // W(-1) replaced by W(1); done by choosing the rows read
+        const int rm = AXIS && axis_face ? ty + 1 : ty - 1;
+        const int rl = AXIS && axis_face ? ty : ty - 1;
+        wload(rm, tx + 1, Wm); wload(ty, tx + 1, Wl); wload(ty + 1, tx + 1, Wr);
+        wload(ty + 2, tx + 1, Wp);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) { GA[c] = sE[c][ty - 1][tx]; GB[c] = sE[c][ty][tx]; }
+        face_flux(GA, GB, sE[5][rl][tx], sE[5][ty][tx], sE[6][ty - 1][tx], sE[6][ty][tx],
+                  sE[7][ty - 1][tx], sE[7][ty][tx], Wm, Wl, Wr, Wp, phys_ef, ph, F);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sFe[c][ty][tx] = F[c];
+      }
+    }
+    if (ONCE) __syncthreads();
     if (interior && kk >= k0) {
-      // in-plane faces (output planes only); W = Q with E replaced by E + p
+      // in-plane faces (output planes only)
       T rhs[5] = {0, 0, 0, 0, 0};
-      if (kk < k1) {
+      if (ONCE && kk < k1) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+          rhs[c] = sFx[c][ty][tx + 1] - sFx[c][ty][tx] + sFe[c][ty + 1][tx] - sFe[c][ty][tx];
+      } else if (!ONCE && kk < k1) {
         // sliding window along each in-plane direction: the face -1/2 uses
         // points -2..1, the face +1/2 points -1..2
         T Wm[5], Wl[5], Wr[5], Wp[5], Fm[5], Fp[5];
-        auto wload = [&](int yy, int xx, T w[5]) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) w[c] = sQ[c][yy][xx];
-          w[4] = sQ[4][yy][xx] + sP[4][yy][xx];
-        };
         {
           T GA[5], GB[5];
           wload(ty + 1, tx - 1, Wm); wload(ty + 1, tx, Wl); wload(ty + 1, tx + 1, Wr);
@@ -370,7 +434,11 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     lbz = po.lb[2];
     nuz = po.nu[2];
     Vz = in.V;
-    if (NB == 1) __syncthreads();      // plane kk is read until here
+    // plane kk is read by other threads until here; with the faces evaluated
+    // once, the barrier after the face fluxes already orders those reads
+    // (what follows reads only the thread's own column, which the next
+    // plane's border writes never touch)
+    if (NB == 1 && !ONCE) __syncthreads();
     if (more) {
       // plane kk+1 goes to LDS: own column and ring-2 border
 #pragma unroll

@@ -158,8 +158,10 @@ class Brute:
         return "sub", [rho, src[1] + (qf - qs) * n[0], src[2] + (qf - qs) * n[1],
                        src[3] + (qf - qs) * n[2], rho * af * af / g]
 
-    def fill(self, Q):
-        """Padded state dict from the interior array Q (5, nth, nr, nx)."""
+    def fill(self, Q, held=None):
+        """Padded state dict from the interior array Q (5, nth, nr, nx).
+        held: padded state dict of Q^n (schedule "step"): its centerline row
+        and physical-face ghosts are taken, not evaluated."""
         nx, nr, nth = self.n
         g = NG
         prm = self.prm
@@ -171,7 +173,11 @@ class Brute:
                 for i in range(nx):
                     S[(i, j, k)] = [float(Q[c, k, j, i]) for c in range(5)]
         axis_node = bc[2] == "axis_node"
-        if axis_node:
+        if axis_node and held is not None:
+            for i in range(nx):
+                for k in range(nth):
+                    S[(i, 0, k)] = list(held[(i, 0, k)])
+        elif axis_node:
             # centerline: mean over the azimuth of the row j = 1, for every k
             for i in range(nx):
                 mean = [sum(S[(i, 1, k)][c] for k in range(nth)) / nth for c in range(5)]
@@ -183,7 +189,9 @@ class Brute:
             for m in range(1, g + 1):
                 for p in self._points_on_plane(d, g, -m):
                     kind = bc[2 * d]
-                    if kind == "periodic":
+                    if held is not None and kind in ("inflow", "outflow", "farfield"):
+                        S[p] = list(held[p])
+                    elif kind == "periodic":
                         S[p] = list(S[self._shift(p, d, nd)])
                     elif kind == "axis":
                         i, j, k = p
@@ -211,7 +219,9 @@ class Brute:
                 for p in self._points_on_plane(d, g, nd - 1 + m):
                     kind = bc[2 * d + 1]
                     e_pt = self._shift(p, d, -m)
-                    if kind == "periodic":
+                    if held is not None and kind in ("inflow", "outflow", "farfield"):
+                        S[p] = list(held[p])
+                    elif kind == "periodic":
                         S[p] = list(S[self._shift(p, d, -nd)])
                     elif kind == "outflow":
                         e = self.prim(S[e_pt])
@@ -255,23 +265,13 @@ class Brute:
                       for m in range(3)]
         return out
 
-    def point_flux(self, S, p, d):
-        """Inviscid minus viscous point flux along d at p (5 components)."""
+    def viscosity(self, S, p):
+        """(mu, mu_sgs) at p in jet-viscosity units: Sutherland and the SGS
+        model of the parameters."""
         prm = self.prm
-        gam = prm["gamma"]
         Cv = prm["visc_coef"]
-        Sm, V = self.metric(p)
-        Sd = Sm[d]
+        _, V = self.metric(p)
         P = self.point(S, p)
-        q = P["q"]
-        Uc = Sd[0] * P["u"] + Sd[1] * P["v"] + Sd[2] * P["w"]
-        F = [P["rho"] * Uc,
-             q[1] * Uc + P["p"] * Sd[0],
-             q[2] * Uc + P["p"] * Sd[1],
-             q[3] * Uc + P["p"] * Sd[2],
-             (q[4] + P["p"]) * Uc]
-        if Cv == 0.0:
-            return F
         gr = self.gradients(S, p)
         g = [gr["u"], gr["v"], gr["w"]]
         T = P["T"]
@@ -296,6 +296,29 @@ class Brute:
             aa = sum(alpha[i][j] ** 2 for i in range(3) for j in range(3))
             c = 2.5 * prm["Cs"] ** 2
             mut = P["rho"] * c * math.sqrt(B / aa) / Cv if aa > 0.0 and B > 0.0 else 0.0
+        return mu, mut
+
+    def point_flux(self, S, p, d, visc=None):
+        """Inviscid minus viscous point flux along d at p (5 components);
+        visc: held {point: (mu, mu_sgs)} (schedule "step")."""
+        prm = self.prm
+        gam = prm["gamma"]
+        Cv = prm["visc_coef"]
+        Sm, V = self.metric(p)
+        Sd = Sm[d]
+        P = self.point(S, p)
+        q = P["q"]
+        Uc = Sd[0] * P["u"] + Sd[1] * P["v"] + Sd[2] * P["w"]
+        F = [P["rho"] * Uc,
+             q[1] * Uc + P["p"] * Sd[0],
+             q[2] * Uc + P["p"] * Sd[1],
+             q[3] * Uc + P["p"] * Sd[2],
+             (q[4] + P["p"]) * Uc]
+        if Cv == 0.0:
+            return F
+        gr = self.gradients(S, p)
+        g = [gr["u"], gr["v"], gr["w"]]
+        mu, mut = visc[p] if visc is not None else self.viscosity(S, p)
         div = g[0][0] + g[1][1] + g[2][2]
         tau = [[(mu + mut) * (g[i][j] + g[j][i] - (2.0 / 3.0 if i == j else 0.0) * div)
                 for j in range(3)] for i in range(3)]
@@ -329,13 +352,13 @@ class Brute:
         q = S[p]
         return [q[0], q[1], q[2], q[3], q[4] + self.point(S, p)["p"]]
 
-    def face(self, S, L, d):
+    def face(self, S, L, d, visc=None):
         """Numerical flux at the face between L and L + e_d."""
         prm = self.prm
         R = self._shift(L, d, 1)
         axis_face = prm["bc"][2] == "axis_node" and d == 1 and L[1] == 0
-        GL = [0.0] * 5 if axis_face else self.point_flux(S, L, d)
-        GR = self.point_flux(S, R, d)
+        GL = [0.0] * 5 if axis_face else self.point_flux(S, L, d, visc)
+        GR = self.point_flux(S, R, d, visc)
         e2 = prm["k2"] * max(self.sensor(S, L, d), self.sensor(S, R, d))
         e4 = max(0.0, prm["k4"] - e2)
         if axis_face:     # the axis point has V = 0: lambda_bar of the j = 1 point
@@ -358,9 +381,10 @@ class Brute:
             out.append(0.5 * (GL[c] + GR[c]) - Vf * dis)
         return out
 
-    def residual(self, Q):
-        """R (5, nth, nr, nx) as nested lists -> returned as a dict of points."""
-        S = self.fill(Q)
+    def residual(self, Q, held=None, visc=None):
+        """R (5, nth, nr, nx) as nested lists -> returned as a dict of points.
+        held, visc: schedule "step" (see fill and point_flux)."""
+        S = self.fill(Q, held)
         nx, nr, nth = self.n
         R = {}
         for k in range(nth):
@@ -372,9 +396,46 @@ class Brute:
                         continue
                     acc = [0.0] * 5
                     for d in range(3):
-                        Fp = self.face(S, p, d)
-                        Fm = self.face(S, self._shift(p, d, -1), d)
+                        Fp = self.face(S, p, d, visc)
+                        Fm = self.face(S, self._shift(p, d, -1), d, visc)
                         acc = [a + fp - fm for a, fp, fm in zip(acc, Fp, Fm)]
                     V = self.metric(p)[1]
                     R[p] = [a / V for a in acc]
         return R, S
+
+    def step(self, Q, dt, schedule="stage"):
+        """One five-stage step Q^(l) = Q^n - alpha_l dt R(Q^(l-1)) of the
+        interior array Q (indexable as Q[c, k, j, i]); schedule "step"
+        evaluates the ghosts of physical faces, the centerline row and
+        (mu, mu_sgs) from Q^n only and holds them through the stages.
+        Returns {point: 5 values}."""
+        nx, nr, nth = self.n
+        held = visc = None
+        if schedule == "step":
+            held = self.fill(Q)
+            if self.prm["visc_coef"] != 0.0:
+                visc = {}
+                for p in held:
+                    i, j, k = p
+                    # region one; axis points (V = 0) carry no viscous flux
+                    if -1 <= i <= nx and -1 <= j <= nr and -1 <= k <= nth and \
+                            self.metric(p)[1] != 0.0:
+                        visc[p] = self.viscosity(held, p)
+        pts = [(i, j, k) for k in range(nth) for j in range(nr) for i in range(nx)]
+        Q0 = {p: [float(Q[c, p[2], p[1], p[0]]) for c in range(5)] for p in pts}
+        cur = Q0
+        for a in self.prm["rk_alpha"]:
+            R, _ = self.residual(_PointArray(cur), held, visc)
+            cur = {p: [Q0[p][c] - a * dt * R[p][c] for c in range(5)] for p in pts}
+        return cur
+
+
+class _PointArray:
+    """Q[c, k, j, i] view of a {(i, j, k): 5 values} dict."""
+
+    def __init__(self, D):
+        self.D = D
+
+    def __getitem__(self, idx):
+        c, k, j, i = idx
+        return self.D[(i, j, k)][c]

@@ -76,6 +76,18 @@ also listed in the design notes):
   C5  boundary normals of axis points (entrance, exit) are those of the
       j = 1 point (S^xi vanishes on the axis);
   C6  the time step maximum runs over j >= 1.
+  Update schedule (prm["schedule"]; section "The JAZzY code", the iteration
+  loop: viscosity, SGS viscosity and boundary conditions are updated once
+  per iteration, after the time marching):
+  L1  "stage" (default): R13/R14, everything recomputed for every stage;
+      "step": mu and mu_t are evaluated once per step from Q^n (equal to
+      the paper's end-of-iteration update of the previous step) and held
+      through the five stages;
+  L2  "step": ghost values of physical faces (entrance, exit, far field) and
+      the centerline average are evaluated once per step from Q^n and held;
+      periodic and cross-axis ghosts are copies of the stage state (the
+      paper's data exchanges, done for every stage); edge ghosts that copy
+      a physical-face ghost take the held value.
 
 The code is dtype-generic: complex128 arrays give complex-step derivatives
 (abs, max and branch tests act on real parts).
@@ -290,8 +302,11 @@ def _unit(Svec):
     return Svec / mag
 
 
-def fill_ghosts(Qp, geo, prm, inflow=None):
+def fill_ghosts(Qp, geo, prm, inflow=None, held=None):
     """Fill the two ghost layers of the padded state in place.
+
+    held: a padded state filled earlier (Q^n of schedule "step", L2) whose
+    physical-face ghosts and centerline row are taken instead of evaluated.
 
     Order xi, eta, zeta (so that edge ghosts read already-filled values):
       xi-  periodic | entrance (data `inflow` = target primitives (5, nth, nr))
@@ -309,12 +324,21 @@ def fill_ghosts(Qp, geo, prm, inflow=None):
     n = (nx, nr, nth)
 
     axis_node = bc[2] == "axis_node"
-    if axis_node:                                   # (C1) axis row = mean of row j = 1
+    if axis_node and held is not None:              # (L2) held centerline row
+        Qp[:, g:g + nth, g, g:g + nx] = held[:, g:g + nth, g, g:g + nx]
+    elif axis_node:                                 # (C1) axis row = mean of row j = 1
         ring = Qp[:, g:g + nth, g + 1, g:g + nx]
         Qp[:, g:g + nth, g, g:g + nx] = np.mean(ring, axis=1, keepdims=True)
     for d in range(3):
         lo_kind, hi_kind = bc[2 * d], bc[2 * d + 1]
         L = _fill_region(Qp, d, g)                  # (5, a, b, n_d + 2g)
+        if held is not None:                        # (L2) held physical-face ghosts
+            Lh = _fill_region(held, d, g)
+            nd = n[d]
+            if lo_kind in PHYSICAL_FACE_KINDS:
+                L[..., :g] = Lh[..., :g]
+            if hi_kind in PHYSICAL_FACE_KINDS:
+                L[..., g + nd:] = Lh[..., g + nd:]
         Sd = _fill_region(S[d], d, g)               # (3, a, b, n_d + 2g)
         if axis_node and d == 0:                    # (C5) normals of the row j = 1
             Sd = Sd.copy()
@@ -335,6 +359,8 @@ def fill_ghosts(Qp, geo, prm, inflow=None):
             for m in range(1, g + 1):
                 L[..., g - m] = np.roll(L[..., g + m], -(n[2] // 2), axis=1)
 
+        if held is not None:
+            continue
         if lo_kind == "inflow":
             Qe = L[..., g]
             e = primitives(Qe, gamma)
@@ -387,14 +413,17 @@ def _lines(A, d, ng):
     return np.moveaxis(A[tuple(sl)], _axis(A, d), -1)
 
 
-def point_terms(Qp, geo, prm):
+def point_terms(Qp, geo, prm, visc=None):
     """Point quantities on the region where every index is in [-1, n].
+
+    visc: held (mu, mu_t) over that region (schedule "step", L1), used in
+    place of the values of this state.
 
     Returns dict with (arrays over that region, shape (.., nth+2, nr+2, nx+2)):
       G[d]    = Fe^d - Fv^d, the inviscid minus viscous point flux (5 comps)
       lam[d]  = spectral radius lambda_d, lam_bar[d] its anisotropic scaling
       nu[d]   = pressure sensor along d
-      mu_t    = SGS eddy viscosity (in jet-viscosity units)
+      mu, mu_t = molecular and SGS eddy viscosity (jet-viscosity units)
     and W over the whole padded box."""
     gamma = prm["gamma"]
     Cv = prm["visc_coef"]
@@ -468,7 +497,9 @@ def point_terms(Qp, geo, prm):
             mu_t = np.where(ok, rho1 * (2.5 * prm["Cs"] ** 2) * ratio / Cv, 0.0 * rho1)
         else:
             mu_t = np.zeros_like(mu)
-        out["mu_t"] = mu_t
+        if visc is not None:                                # (L1) held viscosities
+            mu, mu_t = visc
+        out["mu"], out["mu_t"] = mu, mu_t
         tau = [[(mu + mu_t) * (gu[i][j] + gu[j][i] - (2.0 / 3.0 if i == j else 0.0) * div)
                 for j in range(3)] for i in range(3)]
         kap = (mu / prm["Pr"] + mu_t / prm["Pr_sgs"]) / (gamma - 1.0)
@@ -544,12 +575,13 @@ def face_fluxes(pt, d, prm):
     return 0.5 * (GL + GR) - V_f * dis
 
 
-def residual(Qp, geo, prm):
+def residual(Qp, geo, prm, visc=None):
     """R = RHS / V on the interior, for a padded state whose ghosts are
-    filled; dQ/dt = -R (eq. spatial_discret with unit index spacing)."""
+    filled; dQ/dt = -R (eq. spatial_discret with unit index spacing).
+    visc: held viscosities (see point_terms)."""
     axis_node = prm["bc"][2] == "axis_node"
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-        pt = point_terms(Qp, geo, prm)
+        pt = point_terms(Qp, geo, prm, visc)
         rhs = 0.0
         for d in range(3):
             F = face_fluxes(pt, d, prm)
@@ -605,13 +637,34 @@ def jameson_rk(Q0, resid, dt, alpha):
     return Q
 
 
+def held_state(Q, geo, prm, inflow=None):
+    """Schedule "step" (L1, L2): the padded Q^n with its ghosts filled, and
+    its viscosities (mu, mu_t) on region one (None when inviscid)."""
+    Hp = pad_state(np.asarray(Q))
+    fill_ghosts(Hp, geo, prm, inflow)
+    if prm["visc_coef"] == 0.0:
+        return Hp, None
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        pt = point_terms(Hp, geo, prm)
+    return Hp, (pt["mu"], pt["mu_t"])
+
+
 def rk5_step(Q, geo, prm, inflow=None, dt=None):
     """One RK5 time step of the interior state Q; dt from CFL when None.
     Returns (Q^{n+1}, dt)."""
     if dt is None:
         dt = time_step(Q, geo, prm)
-    Qn = jameson_rk(np.asarray(Q), lambda q: evaluate(q, geo, prm, inflow), dt,
-                    prm["rk_alpha"])
+    if prm.get("schedule", "stage") == "step":
+        Hp, visc = held_state(Q, geo, prm, inflow)
+
+        def resid(q):
+            Qp = pad_state(q)
+            fill_ghosts(Qp, geo, prm, inflow, held=Hp)
+            return residual(Qp, geo, prm, visc)
+    else:
+        def resid(q):
+            return evaluate(q, geo, prm, inflow)
+    Qn = jameson_rk(np.asarray(Q), resid, dt, prm["rk_alpha"])
     return Qn, dt
 
 

@@ -68,6 +68,21 @@ enum les_precision {
                              RK accumulation Q^n - alpha dt R in FP64 */
 };
 
+/* When the viscosities and boundary values are updated during an RK5 step
+ * (section "The JAZzY code": the paper's iteration loop updates the
+ * viscosity, the SGS viscosity and the boundary conditions once per
+ * iteration, after the time marching). */
+enum les_schedule {
+  LES_SCHEDULE_STAGE = 0, /* everything recomputed from the state of every stage */
+  LES_SCHEDULE_STEP = 1   /* mu + mu_sgs (and the conductivity) evaluated at
+                             stage 1 from Q^n and held through the five stages;
+                             ghosts of the entrance, exit and far-field faces
+                             and the centerline row (LES_BC_AXIS_NODE) held
+                             from Q^n; periodic and cross-axis ghosts copied
+                             from each stage state.  Affects les_rk5_step only
+                             (a single residual is the same in both). */
+};
+
 enum les_bc {
   LES_BC_PERIODIC = 0,    /* both faces of a direction; translation `period` */
   LES_BC_AXIS = 1,        /* eta-: ghosts are the points across the axis
@@ -118,6 +133,7 @@ typedef struct les_params {
   double p_exit;              /* exit back pressure */
   int32_t sgs_model;          /* enum les_sgs */
   int32_t precision;          /* enum les_precision */
+  int32_t schedule;           /* enum les_schedule */
 } les_params;
 
 /* ---- host-only helpers (no device work; callable without a GPU) -------- */
@@ -189,7 +205,8 @@ int les_residual_reference(les_ctx* c, void* Q, void* R, void* stream);
 /* Advance Qn (device, FP64, padded, 5 variables) by `nsteps` Jameson RK5
  * steps (section "Time Marching Method"):
  *   Q^(0) = Q^n,  Q^(l) = Q^(0) - alpha_l dt R(Q^(l-1)),  Q^(n+1) = Q^(5),
- * ghosts refilled before every residual.  dt_fixed > 0 uses that step;
+ * ghosts refilled before every residual (LES_SCHEDULE_STEP: see
+ * les_schedule for what is held from Q^n).  dt_fixed > 0 uses that step;
  * dt_fixed <= 0 takes dt = cfl / max over the interior of
  * (lambda_xi + lambda_eta + lambda_zeta) of Q^n each step.  If `dt_out`
  * (device, nsteps doubles) is not NULL the steps used are stored there.
@@ -227,8 +244,8 @@ int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, do
  * kernels.  Qn as in les_rk5_step (ghosts overwritten, interior unchanged);
  * ghost entries of Qbar_np1 are ignored, those of Qbar_n are zero;
  * Qbar_n may alias Qbar_np1; inflow_bar as in les_residual_vjp (added to).
- * FP64 only.  Holds 25 more padded variables after the first call.
- * Asynchronous on `stream`. */
+ * FP64 and LES_SCHEDULE_STAGE only (LES_EUNSUPPORTED otherwise).  Holds 25
+ * more padded variables after the first call.  Asynchronous on `stream`. */
 int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, double* Qbar_n,
                      double* inflow_bar, void* stream);
 

@@ -16,6 +16,8 @@ LIB_PATH = os.environ.get("LESJET_LIB") or os.path.join(
 LES_OK, LES_EINVAL, LES_ENOMEM, LES_EHIP, LES_ENONFINITE, LES_ESTATE, LES_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 LES_FP64, LES_FP32_STORAGE = 0, 1
+LES_SCHEDULE_STAGE, LES_SCHEDULE_STEP = 0, 1
+SCHEDULE = {"stage": 0, "step": 1}
 BC = {"periodic": 0, "axis": 1, "inflow": 2, "outflow": 3, "farfield": 4, "axis_node": 5}
 SGS = {0: 0, 1: 1, 2: 2, "none": 0, "smagorinsky": 1, "vreman": 2}
 STATUS = {0: "LES_OK", -1: "LES_EINVAL", -2: "LES_ENOMEM", -3: "LES_EHIP",
@@ -39,6 +41,7 @@ class les_params(ctypes.Structure):
         ("rk_alpha", ctypes.c_double * 5), ("ref_prim", ctypes.c_double * 5),
         ("p_exit", ctypes.c_double),
         ("sgs_model", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
     ]
 
 
@@ -60,6 +63,8 @@ def make_params(prm, shape, precision=LES_FP64):
     sgs = prm.get("sgs_model", 1)
     p.sgs_model = SGS[sgs] if isinstance(sgs, str) else int(sgs)
     p.precision = int(precision)
+    sch = prm.get("schedule", "stage")
+    p.schedule = SCHEDULE[sch] if isinstance(sch, str) else int(sch)
     return p
 
 

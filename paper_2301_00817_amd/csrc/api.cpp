@@ -26,7 +26,9 @@ struct les_ctx {
   double* coords = nullptr;    // padded coordinates (3 ghost layers), freed by les_metrics
   void* M = nullptr;           // metrics, 10 padded variables of the storage type
   double* inflow = nullptr;    // entrance target primitives (5, nth, nr)
-  void* stage[2] = {nullptr, nullptr};   // RK stage states (storage type)
+  void* stage[3] = {nullptr, nullptr, nullptr};   // RK stage states (storage type; the
+                                                 // third for FP32 with held boundary values)
+  void* visc = nullptr;        // held mu + mu_sgs and conductivity (2 padded variables)
   void* R = nullptr;           // residual buffer (storage type)
   void* PT = nullptr;          // point-quantity scratch of the two-pass residual
   double* part = nullptr;      // per-block partial sums of the diagnostics
@@ -134,6 +136,10 @@ static int validate(const les_params* p, std::string& why) {
     return LES_EINVAL;
   }
   if (p->precision != LES_FP64 && p->precision != LES_FP32_STORAGE) { why = "unknown precision"; return LES_EINVAL; }
+  if (p->schedule != LES_SCHEDULE_STAGE && p->schedule != LES_SCHEDULE_STEP) {
+    why = "unknown schedule";
+    return LES_EINVAL;
+  }
   return LES_OK;
 }
 
@@ -187,12 +193,13 @@ static size_t storage_size(const les_params* p) {
 }
 
 static void free_all(les_ctx* c) {
-  void* ptrs[] = {c->coords, c->M, c->inflow, c->stage[0], c->stage[1], c->R, c->PT,
-                  c->part, c->adj, c->adj_stage, c->maxbits, c->dt, c->flag};
+  void* ptrs[] = {c->coords, c->M, c->inflow, c->stage[0], c->stage[1], c->stage[2], c->visc,
+                  c->R, c->PT, c->part, c->adj, c->adj_stage, c->maxbits, c->dt, c->flag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   c->coords = nullptr; c->M = nullptr; c->inflow = nullptr;
-  c->stage[0] = c->stage[1] = nullptr;
+  c->stage[0] = c->stage[1] = c->stage[2] = nullptr;
+  c->visc = nullptr;
   c->R = nullptr; c->PT = nullptr; c->part = nullptr;
   c->adj = nullptr; c->adj_stage = nullptr;
   c->maxbits = nullptr; c->dt = nullptr; c->flag = nullptr;
@@ -253,8 +260,14 @@ int les_device_bytes(const les_params* p, size_t* bytes) {
   if (r != LES_OK) return fail(nullptr, r, why);
   const size_t ts = storage_size(p);
   // metrics + two stage states (the two-pass reference form adds 21 scratch
-  // variables when it is used)
-  *bytes = (size_t)g.vs * ts * (10 + 5 + 5) + (size_t)5 * p->nth * p->nr * sizeof(double);
+  // variables when it is used); the per-step schedule adds the two held
+  // viscosities and, in FP32, a third stage state
+  size_t vars = 10 + 5 + 5;
+  if (p->schedule == LES_SCHEDULE_STEP) {
+    if (p->visc_coef != 0.0) vars += 2;
+    if (p->precision == LES_FP32_STORAGE) vars += 5;
+  }
+  *bytes = (size_t)g.vs * ts * vars + (size_t)5 * p->nth * p->nr * sizeof(double);
   return LES_OK;
 }
 
@@ -343,20 +356,26 @@ static int ready(les_ctx* c) {
 
 template <typename T>
 static hipError_t ghosts(les_ctx* c, T* Q, hipStream_t s);
+template <typename T>
+static const Phys<T>& phys(les_ctx* c);
 
 template <>
 hipError_t ghosts<double>(les_ctx* c, double* Q, hipStream_t s) {
   return launch_ghosts<double>(Q, c->g, (const double*)c->M, c->inflow, c->ph64, c->p.bc,
-                               c->p.ref_prim, c->p.p_exit, s);
+                               c->p.ref_prim, c->p.p_exit, nullptr, s);
 }
 template <>
 hipError_t ghosts<float>(les_ctx* c, float* Q, hipStream_t s) {
   return launch_ghosts<float>(Q, c->g, (const float*)c->M, c->inflow, c->ph32, c->p.bc,
-                              c->p.ref_prim, c->p.p_exit, s);
+                              c->p.ref_prim, c->p.p_exit, nullptr, s);
+}
+// Ghosts with the physical-face values and centerline row of `held`.
+template <typename T>
+static hipError_t ghosts_held(les_ctx* c, T* Q, const T* held, hipStream_t s) {
+  return launch_ghosts<T>(Q, c->g, (const T*)c->M, c->inflow, phys<T>(c), c->p.bc,
+                          c->p.ref_prim, c->p.p_exit, held, s);
 }
 
-template <typename T>
-static const Phys<T>& phys(les_ctx* c);
 template <>
 const Phys<double>& phys<double>(les_ctx* c) { return c->ph64; }
 template <>
@@ -369,7 +388,7 @@ static int residual_into(les_ctx* c, T* Q, T* R_out, hipStream_t s) {
   if (e == hipSuccess) {
     const long k = prof_begin(c, s);
     e = launch_fused<T>(Q, (const T*)c->M, c->g, phys<T>(c), c->kc, FUSED_EPI_R, R_out, nullptr,
-                        nullptr, 0.0, nullptr, c->ph64, nullptr, s);
+                        nullptr, 0.0, nullptr, c->ph64, nullptr, FUSED_LAG_NONE, nullptr, s);
     prof_end(c, k, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "residual kernel");
@@ -422,21 +441,27 @@ int les_residual(les_ctx* c, void* Q, void* R, void* stream) {
 template <typename T>
 static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double* dt_out,
                      hipStream_t s) {
-  const size_t fb = (size_t)5 * c->g.vs * sizeof(T);
-  int r = dalloc(c, &c->stage[0], fb, "stage state");
-  if (r == LES_OK) r = dalloc(c, &c->stage[1], fb, "stage state");
-  if (r != LES_OK) return r;
   const bool fp32 = sizeof(T) == sizeof(float);
+  // LES_SCHEDULE_STEP: stage 1 fills the ghosts of Q^n (its state buffer is
+  // kept through the step as `held`) and stores the viscosities; stages 2-5
+  // copy the physical-face ghosts from it and read the held viscosities
+  const bool held_sched = c->p.schedule == LES_SCHEDULE_STEP;
+  const int lagv = held_sched && c->ph64.viscous;
+  const int nbuf = fp32 && held_sched ? 3 : 2;   // FP64 keeps Q^n in Qn itself
+  const size_t fb = (size_t)5 * c->g.vs * sizeof(T);
+  int r = LES_OK;
+  for (int b = 0; b < nbuf && r == LES_OK; ++b) r = dalloc(c, &c->stage[b], fb, "stage state");
+  if (r == LES_OK && lagv) r = dalloc(c, &c->visc, (size_t)2 * c->g.vs * sizeof(T), "held viscosities");
+  if (r != LES_OK) return r;
   const bool cfl = dt_fixed <= 0.0;
-  T* S0 = (T*)c->stage[0];
-  T* S1 = (T*)c->stage[1];
+  T* B[3] = {(T*)c->stage[0], (T*)c->stage[1], (T*)c->stage[2]};
   const T* M = (const T*)c->M;
   hipError_t e = launch_reset(c->maxbits, c->flag, s);
   // FP32 storage: the stage-0 state is an FP32 copy of Q^n
   T* cur = (T*)Qn;
   if (fp32 && e == hipSuccess) {
-    e = launch_to_float(Qn, (float*)S1, (long long)5 * c->g.vs, s);
-    cur = S1;
+    e = launch_to_float(Qn, (float*)B[1], (long long)5 * c->g.vs, s);
+    cur = B[1];
   }
   for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
     // dt of this step: the first step reduces over Q^n here, later steps
@@ -448,23 +473,28 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
     if (e == hipSuccess)
       e = launch_dt_finalize(c->maxbits, c->p.cfl, dt_fixed, c->dt, dt_out ? dt_out + n : nullptr,
                              c->flag, s);
+    T* const held = cur;
     T* src = cur;
     for (int l = 0; l < 5 && e == hipSuccess; ++l) {
-      e = ghosts<T>(c, src, s);
+      e = l > 0 && held_sched ? ghosts_held<T>(c, src, held, s) : ghosts<T>(c, src, s);
       if (e != hipSuccess) break;
-      T* dst;
+      // destination: a buffer other than the source and, while later stages
+      // still copy from it, other than the held state
+      T* dst = nullptr;
       double* q64 = nullptr;
       int epi = FUSED_EPI_RK;
-      if (l < 4) {
-        dst = (src == S0) ? S1 : S0;
+      if (l == 4) epi = (cfl && n + 1 < nsteps) || fp32 ? FUSED_EPI_RK_LAST : FUSED_EPI_RK;
+      if (l == 4 && !fp32) {
+        dst = (T*)Qn;
       } else {
-        epi = (cfl && n + 1 < nsteps) || fp32 ? FUSED_EPI_RK_LAST : FUSED_EPI_RK;
-        if (fp32) { dst = (src == S0) ? S1 : S0; q64 = Qn; }   // Q^(n+1) in FP64 + FP32 copy
-        else dst = (T*)Qn;
+        for (int b = 0; b < nbuf && !dst; ++b)
+          if (B[b] != src && !(held_sched && l < 4 && B[b] == held)) dst = B[b];
+        if (l == 4) q64 = Qn;          // Q^(n+1) in FP64 + its FP32 copy
       }
+      const int lag = !lagv ? FUSED_LAG_NONE : (l == 0 ? FUSED_LAG_WRITE : FUSED_LAG_READ);
       const long k = prof_begin(c, s);
       e = launch_fused<T>(src, M, c->g, phys<T>(c), c->kc, epi, dst, Qn, q64, c->p.rk_alpha[l],
-                          c->dt, c->ph64, c->maxbits, s);
+                          c->dt, c->ph64, c->maxbits, lag, (T*)c->visc, s);
       prof_end(c, k, s);
       src = dst;
     }
@@ -540,6 +570,14 @@ static int adjoint_ready(les_ctx* c) {
   return LES_OK;
 }
 
+static int step_adjoint_ready(les_ctx* c) {
+  int r = adjoint_ready(c);
+  if (r != LES_OK) return r;
+  if (c->p.schedule != LES_SCHEDULE_STAGE)
+    return fail(c, LES_EUNSUPPORTED, "the step adjoint covers LES_SCHEDULE_STAGE only");
+  return LES_OK;
+}
+
 int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, double* inflow_bar,
                      void* stream) {
   int r = adjoint_ready(c);
@@ -551,7 +589,7 @@ int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, do
 
 int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, double* Qbar_n,
                      double* inflow_bar, void* stream) {
-  int r = adjoint_ready(c);
+  int r = step_adjoint_ready(c);
   if (r != LES_OK) return r;
   if (!Qn || !Qbar_np1 || !Qbar_n) return fail(c, LES_EINVAL, "Qn, Qbar_np1 or Qbar_n is NULL");
   if (Qn == Qbar_np1 || Qn == Qbar_n) return fail(c, LES_EINVAL, "Qn must not alias a cotangent");
@@ -572,7 +610,8 @@ int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, 
     e = ghosts<double>(c, X[l - 1], s);
     if (e == hipSuccess)
       e = launch_fused<double>(X[l - 1], (const double*)c->M, c->g, c->ph64, c->kc, FUSED_EPI_RK,
-                               X[l], Qn, nullptr, al[l - 1], c->dt, c->ph64, c->maxbits, s);
+                               X[l], Qn, nullptr, al[l - 1], c->dt, c->ph64, c->maxbits,
+                               FUSED_LAG_NONE, nullptr, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "rk5 adjoint forward kernels");
   // reverse: b5 = Qbar^(n+1); b(l-1) = -alpha_l dt J(Q^(l-1))^T b(l);

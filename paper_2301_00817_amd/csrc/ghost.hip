@@ -89,10 +89,14 @@ __device__ __forceinline__ void xi_value(const T* __restrict__ Q, const Grid& g,
 
 // One thread per ghost point: the zeta layers of the whole padded plane, the
 // eta layers (i padded, k interior), the xi layers (j, k interior).
+// held != nullptr: a ghost point whose trace ends in a physical-face rule
+// (entrance, exit, far field) takes the value of `held` at the same point,
+// which is that rule evaluated on the held state.
 template <typename T>
 __global__ void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
                             const double* __restrict__ inflow, double gamma, int xlo, int xhi,
-                            int elo, int ehi, double p_exit, BPrim<T> ref) {
+                            int elo, int ehi, double p_exit, BPrim<T> ref,
+                            const T* __restrict__ held) {
   const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
   const long long nz = 2LL * NG * NX * NR, ne = 2LL * NG * NX * g.nth, nxg = 2LL * NG * g.nr * g.nth;
   long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -116,6 +120,13 @@ __global__ void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
     return;
   }
   const int og = g.at(i, j, k);
+  if (held && ((i < 0 && xlo != BC_PERIODIC) || (i >= g.nx && xhi != BC_PERIODIC) ||
+               (j >= g.nr && ehi != BC_PERIODIC))) {
+    T h[5];
+    load5(held, g.vs, og, h);
+    store5(Q, g.vs, og, h);
+    return;
+  }
   // zeta sweep (periodic): the wrapped point
   int kw = k < 0 ? k + g.nth : (k >= g.nth ? k - g.nth : k);
   const int an = elo == BC_AXIS_NODE;
@@ -149,6 +160,16 @@ __global__ void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
 // FP64 tree over k, so the value is the same for every k and reproducible).
 constexpr int CL_BS = 256;
 
+// held row (schedule with held boundary values)
+template <typename T>
+__global__ void k_centerline_held(T* __restrict__ Q, Grid g, const T* __restrict__ held) {
+  const int i = blockIdx.x;
+  for (int k = threadIdx.x; k < g.nth; k += blockDim.x) {
+    const int o = g.at(i, 0, k);
+    for (int c = 0; c < 5; ++c) Q[(long long)c * g.vs + o] = held[(long long)c * g.vs + o];
+  }
+}
+
 template <typename T>
 __global__ void k_centerline(T* __restrict__ Q, Grid g) {
   __shared__ double red[5][CL_BS];
@@ -180,9 +201,13 @@ hipError_t launch_centerline(T* Q, const Grid& g, hipStream_t s) {
 template <typename T>
 hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
                          const Phys<T>& ph, const int bc[6], const double ref_prim[5],
-                         double p_exit, hipStream_t s) {
-  if (bc[2] == BC_AXIS_NODE)
-    hipLaunchKernelGGL(k_centerline<T>, dim3(g.nx), dim3(CL_BS), 0, s, Q, g);
+                         double p_exit, const T* held, hipStream_t s) {
+  if (bc[2] == BC_AXIS_NODE) {
+    if (held)
+      hipLaunchKernelGGL(k_centerline_held<T>, dim3(g.nx), dim3(CL_BS), 0, s, Q, g, held);
+    else
+      hipLaunchKernelGGL(k_centerline<T>, dim3(g.nx), dim3(CL_BS), 0, s, Q, g);
+  }
   const double gamma = (double)ph.gamma;
   BPrim<T> ref;
   ref.rho = (T)ref_prim[0]; ref.u = (T)ref_prim[1]; ref.v = (T)ref_prim[2];
@@ -190,16 +215,16 @@ hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
   const long long NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
   const long long n = 2LL * NG * (NX * NR + NX * g.nth + (long long)g.nr * g.nth);
   hipLaunchKernelGGL(k_ghost_all<T>, dim3(blocks_for(n, 128)), dim3(128), 0, s, Q, g, M, inflow,
-                     gamma, bc[0], bc[1], bc[2], bc[3], p_exit, ref);
+                     gamma, bc[0], bc[1], bc[2], bc[3], p_exit, ref, held);
   return hipGetLastError();
 }
 
 template hipError_t launch_centerline<double>(double*, const Grid&, hipStream_t);
 template hipError_t launch_ghosts<double>(double*, const Grid&, const double*, const double*,
                                           const Phys<double>&, const int*, const double*, double,
-                                          hipStream_t);
+                                          const double*, hipStream_t);
 template hipError_t launch_ghosts<float>(float*, const Grid&, const float*, const double*,
                                          const Phys<float>&, const int*, const double*, double,
-                                         hipStream_t);
+                                         const float*, hipStream_t);
 
 }  // namespace lesjet

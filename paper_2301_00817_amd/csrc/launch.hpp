@@ -17,9 +17,12 @@ hipError_t launch_metrics(const double* C, const CGrid& cg, T* M, const Grid& g,
 template <typename T>
 hipError_t launch_centerline(T* Q, const Grid& g, hipStream_t s);
 
+// held != NULL: ghosts of physical faces (and the centerline row) are
+// copied from `held` (a state filled earlier), the others traced as usual.
 template <typename T>
 hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow, const Phys<T>& ph,
-                         const int bc[6], const double ref_prim[5], double p_exit, hipStream_t s);
+                         const int bc[6], const double ref_prim[5], double p_exit, const T* held,
+                         hipStream_t s);
 
 template <typename T>
 hipError_t launch_residual_ref(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, T* PT,
@@ -31,9 +34,13 @@ int fused_chunk(const Grid& g, int num_cu);
 template <typename T>
 hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, int kc, int epi,
                         T* out, const double* Q0, double* Q64, double alpha, const double* dt,
-                        const Phys<double>& ph64, unsigned long long* maxbits, hipStream_t s);
+                        const Phys<double>& ph64, unsigned long long* maxbits, int lag, T* visc,
+                        hipStream_t s);
 
 enum { FUSED_EPI_R = 0, FUSED_EPI_RK = 1, FUSED_EPI_RK_LAST = 2 };
+// viscosity schedule of the stage kernel (same values as LAG_* of the
+// point formulas): none, write the held values, read them
+enum { FUSED_LAG_NONE = 0, FUSED_LAG_WRITE = 1, FUSED_LAG_READ = 2 };
 
 template <typename TQ, typename TM>
 hipError_t launch_lambda_max(const TQ* Q, const TM* M, const Grid& g, const Phys<double>& ph,

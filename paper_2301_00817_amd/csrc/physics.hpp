@@ -151,6 +151,7 @@ struct PointIn {
   T nu[3];           // pressure sensor along d
   T S[3][3];         // S[d] = J^-1 grad(xi_d)
   T V;               // J^-1
+  T mt, kap;         // held mu + mu_sgs and conductivity (LAG_READ)
 };
 
 // Central differences and pressure sensor along one direction from the
@@ -186,9 +187,14 @@ struct PointOut {
   T G[3][5];
   T lb[3];
   T nu[3];
+  T mt, kap;         // mu + mu_sgs and conductivity of the point (LAG_WRITE)
 };
 
-template <typename T>
+// Viscosity update schedule: computed from the point's own state (LAG_NONE),
+// also returned for holding (LAG_WRITE), or taken from held values (LAG_READ).
+enum { LAG_NONE = 0, LAG_WRITE = 1, LAG_READ = 2 };
+
+template <typename T, int LAG = LAG_NONE>
 __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phys<T>& ph,
                                                  PointOut<T>& out) {
   Prim<T> s;
@@ -219,28 +225,38 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
       for (int m = 0; m < 3; ++m)
         g[f][m] = (in.S[0][m] * dl[0][f] + in.S[1][m] * dl[1][f] + in.S[2][m] * dl[2][f]) * iV;
 
-    const T mu = Tt * a * ph.suth1 * trcp(Tt + ph.suth);      // Sutherland
-    T mut = T(0);
-    if (ph.sgs == 1) {                                        // Smagorinsky
-      T s2 = T(0);
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          const T sij = T(0.5) * (g[i][j] + g[j][i]);
-          s2 += sij * sij;
-        }
-      const T delta = tcbrt(tabs(in.V));
-      mut = s.rho * ph.sgs_coef * delta * delta * tsqrt(T(2) * s2);
-    } else if (ph.sgs == 2) {                                 // Vreman
-      const T delta = tcbrt(tabs(in.V));
-      mut = s.rho * ph.sgs_coef * delta * delta * vreman_ratio(g);
+    T mt, kap;
+    if (LAG == LAG_READ) {
+      mt = in.mt;
+      kap = in.kap;
+    } else {
+      const T mu = Tt * a * ph.suth1 * trcp(Tt + ph.suth);    // Sutherland
+      T mut = T(0);
+      if (ph.sgs == 1) {                                      // Smagorinsky
+        T s2 = T(0);
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            const T sij = T(0.5) * (g[i][j] + g[j][i]);
+            s2 += sij * sij;
+          }
+        const T delta = tcbrt(tabs(in.V));
+        mut = s.rho * ph.sgs_coef * delta * delta * tsqrt(T(2) * s2);
+      } else if (ph.sgs == 2) {                               // Vreman
+        const T delta = tcbrt(tabs(in.V));
+        mut = s.rho * ph.sgs_coef * delta * delta * vreman_ratio(g);
+      }
+      mt = mu + mut;
+      kap = (mu * ph.Pr_inv + mut * ph.Prs_inv) * ph.igm1;
+      if (LAG == LAG_WRITE) {
+        out.mt = mt;
+        out.kap = kap;
+      }
     }
-    const T mt = mu + mut;
     const T div = g[0][0] + g[1][1] + g[2][2];
     T tau[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j)
         tau[i][j] = mt * (g[i][j] + g[j][i] - (i == j ? T(2.0 / 3.0) * div : T(0)));
-    const T kap = (mu * ph.Pr_inv + mut * ph.Prs_inv) * ph.igm1;
     T beta[3];
     for (int j = 0; j < 3; ++j)
       beta[j] = tau[0][j] * s.u + tau[1][j] * s.v + tau[2][j] * s.w + kap * g[3][j];

@@ -125,11 +125,17 @@ template <> struct FusedOcc<float> { static constexpr int waves = 4; };
 
 // AXIS: the eta- face is a centerline through mesh nodes (row j = 0 on the
 // axis); a separate instance so that the common case carries none of it.
-template <typename T, int EPI, bool AXIS>
+// LAG: viscosity schedule (LAG_NONE; LAG_WRITE also stores mu + mu_sgs and
+// the conductivity of every point the block evaluates into `visc`, two
+// padded variables; LAG_READ takes them from there).  The tiling is the same
+// in every stage, so the points read are those written; points shared by
+// two blocks are written twice with the same value.
+template <typename T, int EPI, bool AXIS, int LAG>
 __global__ void __launch_bounds__(Tile<T>::X * Tile<T>::Y, FusedOcc<T>::waves)
 k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, int kc,
         TileMap tm, T* out, const double* Q0, double* Q64, double alpha,
-        const double* __restrict__ dtp, Phys<double> ph64, unsigned long long* __restrict__ maxbits) {
+        const double* __restrict__ dtp, Phys<double> ph64, unsigned long long* __restrict__ maxbits,
+        T* __restrict__ visc) {
   constexpr int FB_X = Tile<T>::X;              // threads along i (ring-1 columns)
   constexpr int FB_Y = Tile<T>::Y;              // threads along j
   constexpr int FT_X = FB_X - 2;                // interior outputs along i
@@ -195,6 +201,16 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
   T Pb[5];               // (u, v, w, T, p) at kk-1
   T Qn[5];               // Q at kk+2, in flight
   T met[10], metn[10];   // metrics at (i, j, kk) and the prefetch for kk+1
+  T lag[2], lagn[2];     // held (mu + mu_sgs, conductivity), same planes (LAG_READ)
+  auto load_lag = [&](int kk, T v[2]) {
+    if (col_ok) {
+      const int o = g.at(i, j, kk);
+      v[0] = visc[o];
+      v[1] = visc[(long long)g.vs + o];
+    } else {
+      v[0] = T(0); v[1] = T(0);
+    }
+  };
   // zeta-face state of plane kk-1 (interior columns)
   T Gz[5], lbz = 0, nuz = 0, Vz = 0;
   T acc[5];              // RHS at kk-1 without its zeta face kk-1/2:
@@ -218,6 +234,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     load_q(Qin, g, i, j, k0, Qd);
     prim5(Qd, ph, Pd);
     load_metrics(M, g, i, j, k0 - 1, col_ok, met);
+    if (LAG == LAG_READ) load_lag(k0 - 1, lag);
   }
 #pragma unroll
   for (int c = 0; c < 5; ++c) { Wb[c] = Wa[c]; Gz[c] = 0; acc[c] = 0; }
@@ -244,6 +261,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
     if (more) {
       if (kk + 2 <= k1 + 1) load_q(Qin, g, i, j, kk + 2, Qn);
       load_metrics(M, g, i, j, kk + 1, col_ok, metn);
+      if (LAG == LAG_READ) load_lag(kk + 1, lagn);
     }
     // (a) plane kk is in LDS (written before the loop or at the end of the
     // previous iteration)
@@ -272,7 +290,13 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
 #pragma unroll
       for (int c = 0; c < 3; ++c) in.S[d][c] = met[3 * d + c];
     in.V = met[9];
-    point_quantities(in, ph, po);
+    if (LAG == LAG_READ) { in.mt = lag[0]; in.kap = lag[1]; }
+    point_quantities<T, LAG>(in, ph, po);
+    if (LAG == LAG_WRITE && col_ok && ph.viscous) {
+      const int o = g.at(i, j, kk);
+      visc[o] = po.mt;
+      visc[(long long)g.vs + o] = po.kap;
+    }
     if (AXIS && axis_row) {
       // centerline through the nodes: S^eta = 0 on the axis, so the eta
       // point flux vanishes (its viscous part, singular at V = 0, is not used)
@@ -459,6 +483,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
       prim5(Qd, ph, Pd);
 #pragma unroll
       for (int c = 0; c < 10; ++c) met[c] = metn[c];
+      if (LAG == LAG_READ) { lag[0] = lagn[0]; lag[1] = lagn[1]; }
     }
   }
 
@@ -500,7 +525,12 @@ int fused_chunk(const Grid& g, int num_cu) {
 template <typename T>
 hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, int kc, int epi,
                         T* out, const double* Q0, double* Q64, double alpha, const double* dt,
-                        const Phys<double>& ph64, unsigned long long* maxbits, hipStream_t s) {
+                        const Phys<double>& ph64, unsigned long long* maxbits, int lag, T* visc,
+                        hipStream_t s) {
+  // instances: LAG_NONE with every epilogue, LAG_WRITE with EPI_RK (stage 1),
+  // LAG_READ with EPI_RK and EPI_RK_LAST (stages 2-5)
+  if (lag != LAG_NONE && (!visc || epi == EPI_R || (lag == LAG_WRITE && epi != EPI_RK)))
+    return hipErrorInvalidValue;
   constexpr int FT_X = Tile<T>::X - 2, FT_Y = Tile<T>::Y - 2;
   TileMap tm;
   tm.gx = (g.nx + FT_X - 1) / FT_X;
@@ -510,18 +540,23 @@ hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph
   tm.per_xcd = (int)((ntiles + NXCD - 1) / NXCD);
   const dim3 grid((unsigned)(tm.per_xcd * NXCD));
   const dim3 block(Tile<T>::X, Tile<T>::Y, 1);
-#define LESJET_FUSED(E, A)                                                                   \
-  hipLaunchKernelGGL((k_fused<T, E, A>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0, Q64, \
-                     alpha, dt, ph64, maxbits)
+#define LESJET_FUSED(E, A, L)                                                                   \
+  hipLaunchKernelGGL((k_fused<T, E, A, L>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0, Q64, \
+                     alpha, dt, ph64, maxbits, visc)
+#define LESJET_FUSED_EPI(A)                                                        \
+  if (lag == LAG_WRITE) LESJET_FUSED(EPI_RK, A, LAG_WRITE);                        \
+  else if (lag == LAG_READ) {                                                      \
+    if (epi == EPI_RK) LESJET_FUSED(EPI_RK, A, LAG_READ);                          \
+    else LESJET_FUSED(EPI_RK_LAST, A, LAG_READ);                                   \
+  } else if (epi == EPI_R) LESJET_FUSED(EPI_R, A, LAG_NONE);                       \
+  else if (epi == EPI_RK) LESJET_FUSED(EPI_RK, A, LAG_NONE);                       \
+  else LESJET_FUSED(EPI_RK_LAST, A, LAG_NONE);
   if (ph.axis_node) {
-    if (epi == EPI_R) LESJET_FUSED(EPI_R, true);
-    else if (epi == EPI_RK) LESJET_FUSED(EPI_RK, true);
-    else LESJET_FUSED(EPI_RK_LAST, true);
+    LESJET_FUSED_EPI(true)
   } else {
-    if (epi == EPI_R) LESJET_FUSED(EPI_R, false);
-    else if (epi == EPI_RK) LESJET_FUSED(EPI_RK, false);
-    else LESJET_FUSED(EPI_RK_LAST, false);
+    LESJET_FUSED_EPI(false)
   }
+#undef LESJET_FUSED_EPI
 #undef LESJET_FUSED
   return hipGetLastError();
 }
@@ -531,10 +566,10 @@ template int fused_chunk<float>(const Grid&, int);
 template hipError_t launch_fused<double>(const double*, const double*, const Grid&,
                                          const Phys<double>&, int, int, double*, const double*,
                                          double*, double, const double*, const Phys<double>&,
-                                         unsigned long long*, hipStream_t);
+                                         unsigned long long*, int, double*, hipStream_t);
 template hipError_t launch_fused<float>(const float*, const float*, const Grid&, const Phys<float>&,
                                         int, int, float*, const double*, double*, double,
                                         const double*, const Phys<double>&, unsigned long long*,
-                                        hipStream_t);
+                                        int, float*, hipStream_t);
 
 }  // namespace lesjet

@@ -114,6 +114,16 @@ struct TileMap {
   int per_xcd;          // ceil(gx gy gz / NXCD)
 };
 
+// The FP64 kernel has registers left at two waves per SIMD: it loads Q^(0)
+// of the output point an iteration ahead (FP32 at 128 VGPRs does not).
+template <typename T> struct PrefetchQ0 { static constexpr bool on = sizeof(T) == 8; };
+#ifdef LESJET_PREF_Q0
+template <> struct PrefetchQ0<double> { static constexpr bool on = LESJET_PREF_Q0 != 0; };
+#endif
+#ifdef LESJET_PREF_Q0_32
+template <> struct PrefetchQ0<float> { static constexpr bool on = LESJET_PREF_Q0_32 != 0; };
+#endif
+
 // Register budget: FP64 two waves per SIMD (242 VGPRs), FP32 four (128).
 template <typename T> struct FusedOcc;
 template <> struct FusedOcc<double> { static constexpr int waves = 2; };
@@ -202,6 +212,9 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
   T Qn[5];               // Q at kk+2, in flight
   T met[10], metn[10];   // metrics at (i, j, kk) and the prefetch for kk+1
   T lag[2], lagn[2];     // held (mu + mu_sgs, conductivity), same planes (LAG_READ)
+  constexpr bool PQ0 = EPI != EPI_R && PrefetchQ0<T>::on;
+  double q0p[5];         // Q^(0) at (i, j, kk-1), loaded at the top of iteration kk
+  const double ad_pre = PQ0 ? alpha * (*dtp) : 0.0;
   auto load_lag = [&](int kk, T v[2]) {
     if (col_ok) {
       const int o = g.at(i, j, kk);
@@ -262,6 +275,11 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
       if (kk + 2 <= k1 + 1) load_q(Qin, g, i, j, kk + 2, Qn);
       load_metrics(M, g, i, j, kk + 1, col_ok, metn);
       if (LAG == LAG_READ) load_lag(kk + 1, lagn);
+    }
+    if (PQ0 && interior && kk - 1 >= k0) {
+      const int o = g.at(i, j, kk - 1);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) q0p[c] = Q0[(long long)c * g.vs + o];
     }
     // (a) plane kk is in LDS (written before the loop or at the end of the
     // previous iteration)
@@ -423,12 +441,12 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
 #pragma unroll
           for (int c = 0; c < 5; ++c) out[(long long)c * g.vs + o] = R[c];
         } else {
-          const double ad = alpha * (*dtp);
+          const double ad = PQ0 ? ad_pre : alpha * (*dtp);
           double qn[5];
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
             const long long oc = (long long)c * g.vs + o;
-            qn[c] = Q0[oc] - ad * (double)R[c];
+            qn[c] = (PQ0 ? q0p[c] : Q0[oc]) - ad * (double)R[c];
             out[oc] = (T)qn[c];
             if (EPI == EPI_RK_LAST && Q64) Q64[oc] = qn[c];
           }

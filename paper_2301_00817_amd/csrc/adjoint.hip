@@ -176,7 +176,10 @@ __device__ __forceinline__ void face_self(const FaceCoef& f, const double* Wm, c
 // function.  Writes the state cotangent of everything that depends on p
 // alone (S_PQ) and the cotangents of p's central differences and sensor
 // neighbour pressures (S_DL, S_NC), which pass 3 hands to the neighbours.
-__global__ __launch_bounds__(256) void k_adj_main(const double* __restrict__ Q,
+#ifndef LESJET_ADJ_MAIN_OCC
+#define LESJET_ADJ_MAIN_OCC 1
+#endif
+__global__ __launch_bounds__(256, LESJET_ADJ_MAIN_OCC) void k_adj_main(const double* __restrict__ Q,
                                                   const double* __restrict__ M, Grid g,
                                                   Phys<double> ph, double* __restrict__ SC) {
   const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG, NT = g.nth + 2 * NG;

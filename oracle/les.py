@@ -76,6 +76,32 @@ also listed in the design notes):
   C5  boundary normals of axis points (entrance, exit) are those of the
       j = 1 point (S^xi vanishes on the axis);
   C6  the time step maximum runs over j >= 1.
+  Dynamic Smagorinsky model (sgs_model 3, subsection "Dynamic Smagorinsky
+  Model"; the isotropic SGS stress enters the momentum and energy fluxes as
+  in the modified System I equations):
+  D1  test filter: the separable three-point filter (1/4, 1/2, 1/4) along
+      each index direction (27 points), test width Delta_hat = 2 Delta;
+  D2  <.> is the volume average over the interior points (weights J^-1);
+      each coefficient is the ratio of two such averages;
+  D3  Delta stays outside the hats (the local width of the averaging
+      point); hat(sigma_ll) = 2 C_I Delta^2 hat(rho |S|^2);
+  D4  T_ll is the trace of L_ij = hat(rho u_i u_j) - hat(rho u_i)
+      hat(rho u_j) / hat(rho); S_ij in the contractions is the resolved
+      strain at the point, S_hat_ij the strain of u_hat = hat(rho u)/hat(rho);
+  D5  mu_sgs = rho C_ds Delta^2 |S| (the printed square of rho C_ds Delta
+      read as for the static model, R7), in jet-viscosity units; C_ds and
+      C_I below 0 are taken as 0 (a negative eddy viscosity or isotropic
+      stress is not used);
+  D6  Pr_sgs = C_ds <Delta^2 hat(rho |S| dT/dx_j) dT/dx_j - Delta_hat^2
+      rho_hat |S_hat| dT_hat/dx_j dT/dx_j> / <(hat(rho u_j T) - hat(rho u_j)
+      hat(rho T)/hat(rho)) dT/dx_j>, T_hat = hat(rho T)/hat(rho); the static
+      0.9 where that is not a positive finite number;
+  D7  the isotropic stress sigma_kk = 2 C_I rho Delta^2 |S|^2 adds
+      sigma_kk / 3 to the pressure of the momentum and energy point fluxes
+      (not to W or the spectral radii);
+  D8  the coefficients are evaluated with the viscosities: from every stage
+      state (schedule "stage"), or from Q^n and held (schedule "step"; the
+      isotropic stress then uses the held C_I and the stage |S|).
   Update schedule (prm["schedule"]; section "The JAZzY code", the iteration
   loop: viscosity, SGS viscosity and boundary conditions are updated once
   per iteration, after the time marching):
@@ -413,11 +439,12 @@ def _lines(A, d, ng):
     return np.moveaxis(A[tuple(sl)], _axis(A, d), -1)
 
 
-def point_terms(Qp, geo, prm, visc=None):
+def point_terms(Qp, geo, prm, visc=None, dyn=None):
     """Point quantities on the region where every index is in [-1, n].
 
     visc: held (mu, mu_t) over that region (schedule "step", L1), used in
-    place of the values of this state.
+    place of the values of this state; dyn: held coefficients of the
+    dynamic model (D8), else computed from this state.
 
     Returns dict with (arrays over that region, shape (.., nth+2, nr+2, nx+2)):
       G[d]    = Fe^d - Fv^d, the inviscid minus viscous point flux (5 comps)
@@ -495,14 +522,31 @@ def point_terms(Qp, geo, prm, visc=None):
             ok = (np.real(aa) > 0.0) & (np.real(B) > 0.0)
             ratio = np.sqrt(np.where(ok, B, 1.0) / np.where(ok, aa, 1.0))
             mu_t = np.where(ok, rho1 * (2.5 * prm["Cs"] ** 2) * ratio / Cv, 0.0 * rho1)
+        elif prm["sgs_model"] == 3:
+            # dynamic model (D1-D8): global coefficients, then the static forms
+            if dyn is None:
+                dyn = dynamic_coefficients(Qp, geo, prm)
+            S2 = 0.0
+            for i in range(3):
+                for j in range(3):
+                    S2 = S2 + (0.5 * (gu[i][j] + gu[j][i])) ** 2
+            Smag2 = 2.0 * S2                                # |S|^2
+            delta2 = rabs(V) ** (2.0 / 3.0)
+            mu_t = rho1 * dyn["C_ds_eff"] * delta2 * np.sqrt(Smag2) / Cv      # (D5)
+            p_sgs = (2.0 / 3.0) * dyn["C_I_eff"] * rho1 * delta2 * Smag2      # (D7)
+            for d in range(3):
+                Fe[d] = Fe[d] + np.stack([0.0 * p_sgs, p_sgs * S[d, 0], p_sgs * S[d, 1],
+                                          p_sgs * S[d, 2], p_sgs * Uc[d]])
         else:
             mu_t = np.zeros_like(mu)
         if visc is not None:                                # (L1) held viscosities
             mu, mu_t = visc
         out["mu"], out["mu_t"] = mu, mu_t
+        out["dyn"] = dyn
+        Pr_sgs = dyn["Pr_eff"] if prm["sgs_model"] == 3 else prm["Pr_sgs"]
         tau = [[(mu + mu_t) * (gu[i][j] + gu[j][i] - (2.0 / 3.0 if i == j else 0.0) * div)
                 for j in range(3)] for i in range(3)]
-        kap = (mu / prm["Pr"] + mu_t / prm["Pr_sgs"]) / (gamma - 1.0)
+        kap = (mu / prm["Pr"] + mu_t / Pr_sgs) / (gamma - 1.0)
         q = [-kap * gT[j] for j in range(3)]                # (R6)
         vel = (u1, v1, w1)
         beta = [tau[0][j] * vel[0] + tau[1][j] * vel[1] + tau[2][j] * vel[2] - q[j]
@@ -544,6 +588,111 @@ def point_terms(Qp, geo, prm, visc=None):
     return out
 
 
+def test_filter(A):
+    """Separable three-point test filter (1/4, 1/2, 1/4) along the last three
+    axes (D1); the result is one point shorter at each end of each axis."""
+    for ax in (-1, -2, -3):
+        n = A.shape[ax]
+        lo = np.take(A, range(0, n - 2), axis=ax)
+        mid = np.take(A, range(1, n - 1), axis=ax)
+        hi = np.take(A, range(2, n), axis=ax)
+        A = 0.25 * lo + 0.5 * mid + 0.25 * hi
+    return A
+
+
+def dynamic_coefficients(Qp, geo, prm):
+    """Coefficients C_I, C_ds and Pr_sgs of the dynamic model (subsection
+    "Dynamic Smagorinsky Model"; readings D1-D6) from a padded state whose
+    ghosts are filled.  Returns the raw ratios, the volume-weighted sums
+    they come from, and the values used (C_I_eff, C_ds_eff, Pr_eff)."""
+    gamma = prm["gamma"]
+    rho, u, v, w, p = primitives(Qp, gamma)
+    T = gamma * p / rho
+    vel = (u, v, w)
+    S_all, V_all = geo["S"], geo["V"]
+
+    def grad_on(phi, S, V):
+        """chain-rule gradient of phi (one point wider than S, V) on the
+        region of S, V."""
+        dd = []
+        for d in range(3):
+            ax = 2 - d
+            hi = [slice(1, -1)] * 3
+            lo = [slice(1, -1)] * 3
+            hi[ax] = slice(2, None)
+            lo[ax] = slice(None, -2)
+            dd.append((phi[tuple(hi)] - phi[tuple(lo)]) / 2.0)
+        return [(S[0, m] * dd[0] + S[1, m] * dd[1] + S[2, m] * dd[2]) / V for m in range(3)]
+
+    r1 = (slice(1, -1),) * 3              # region one of the padded box
+    it = (slice(2, -2),) * 3              # interior of the padded box
+    S1, V1 = S_all[(slice(None), slice(None)) + r1], V_all[r1]
+    Si, Vi = S_all[(slice(None), slice(None)) + it], V_all[it]
+    # resolved strain, |S| and temperature gradient on region one
+    gu = [grad_on(vel[i], S1, V1) for i in range(3)]
+    gT = grad_on(T, S1, V1)
+    Sij = [[0.5 * (gu[i][j] + gu[j][i]) for j in range(3)] for i in range(3)]
+    Smag = np.sqrt(2.0 * sum(Sij[i][j] ** 2 for i in range(3) for j in range(3)))
+    rho1 = rho[r1]
+    # fields filtered from region one to the interior
+    h_rSS = [[test_filter(rho1 * Smag * Sij[i][j]) for j in range(3)] for i in range(3)]
+    h_rS2 = test_filter(rho1 * Smag ** 2)
+    h_rST = [test_filter(rho1 * Smag * gT[j]) for j in range(3)]
+    # state products filtered from the padded box to region one
+    f_r = test_filter(rho)
+    f_ru = [test_filter(rho * vel[i]) for i in range(3)]
+    f_rT = test_filter(rho * T)
+    # ... and their interior part
+    c = (slice(1, -1),) * 3
+    h_r = f_r[c]
+    h_ru = [f_ru[i][c] for i in range(3)]
+    h_rT = f_rT[c]
+    h_ruu = [[test_filter(rho * vel[i] * vel[j])[c] for j in range(3)] for i in range(3)]
+    h_ruT = [test_filter(rho * vel[j] * T)[c] for j in range(3)]
+    # strain of u_hat and gradient of T_hat on the interior (D4, D6)
+    uh = [f_ru[i] / f_r for i in range(3)]
+    guh = [grad_on(uh[i], Si, Vi) for i in range(3)]
+    gTh = grad_on(f_rT / f_r, Si, Vi)
+    Shij = [[0.5 * (guh[i][j] + guh[j][i]) for j in range(3)] for i in range(3)]
+    Shmag = np.sqrt(2.0 * sum(Shij[i][j] ** 2 for i in range(3) for j in range(3)))
+    # resolved quantities at the interior
+    Sc = [[Sij[i][j][c] for j in range(3)] for i in range(3)]
+    Smc = Smag[c]
+    gTc = [gT[j][c] for j in range(3)]
+    D2 = rabs(Vi) ** (2.0 / 3.0)          # Delta^2 (R9)
+    Dh2 = 4.0 * D2                        # Delta_hat = 2 Delta (D1)
+    trS = Sc[0][0] + Sc[1][1] + Sc[2][2]
+    L = [[h_ruu[i][j] - h_ru[i] * h_ru[j] / h_r for j in range(3)] for i in range(3)]
+    Lll = L[0][0] + L[1][1] + L[2][2]
+    LS = sum(L[i][j] * Sc[i][j] for i in range(3) for j in range(3))
+    # C_I (eq. av_ci)
+    N_I = Lll
+    D_I = 2.0 * Dh2 * h_r * Shmag ** 2 - 2.0 * D2 * h_rS2
+    # C_ds (eq. av_cd): numerator = A + C_I B (D3)
+    A = LS - trS * Lll / 3.0
+    B = trS * 2.0 * D2 * h_rS2 / 3.0
+    h_rSS_S = sum(h_rSS[i][j] * Sc[i][j] for i in range(3) for j in range(3))
+    h_rSmm = h_rSS[0][0] + h_rSS[1][1] + h_rSS[2][2]
+    Sh_S = sum(Shij[i][j] * Sc[i][j] for i in range(3) for j in range(3))
+    trSh = Shij[0][0] + Shij[1][1] + Shij[2][2]
+    D_d = (2.0 * D2 * (h_rSS_S - h_rSmm * trS / 3.0)
+           - 2.0 * Dh2 * (h_r * Shmag * Sh_S - h_r * Shmag * trSh * trS / 3.0))
+    # Pr_sgs (eq. av_Pr_sgs, D6)
+    N_P = sum(D2 * h_rST[j] * gTc[j] - Dh2 * h_r * Shmag * gTh[j] * gTc[j] for j in range(3))
+    D_P = sum((h_ruT[j] - h_ru[j] * h_rT / h_r) * gTc[j] for j in range(3))
+    sums = {k: float(np.sum(np.real(Vi * a))) for k, a in
+            dict(N_I=N_I, D_I=D_I, A=A, B=B, D_d=D_d, N_P=N_P, D_P=D_P).items()}
+    C_I = sums["N_I"] / sums["D_I"] if sums["D_I"] != 0.0 else 0.0
+    C_I_eff = max(C_I, 0.0)
+    # C_ds uses the C_I of the isotropic term actually modelled (D3, D5)
+    C_ds = (sums["A"] + C_I_eff * sums["B"]) / sums["D_d"] if sums["D_d"] != 0.0 else 0.0
+    C_ds_eff = max(C_ds, 0.0)
+    Pr = C_ds_eff * sums["N_P"] / sums["D_P"] if sums["D_P"] != 0.0 else float("nan")
+    Pr_eff = Pr if np.isfinite(Pr) and Pr > 0.0 else prm["Pr_sgs"]
+    return dict(C_I=C_I, C_ds=C_ds, Pr_sgs=Pr, C_I_eff=C_I_eff, C_ds_eff=C_ds_eff,
+                Pr_eff=Pr_eff, sums=sums)
+
+
 def face_fluxes(pt, d, prm):
     """Numerical fluxes at the faces -1/2 .. n_d - 1/2 along direction d
     (eq. inv_flux_vec with the dissipation of eq. dissip_term), on the
@@ -575,13 +724,13 @@ def face_fluxes(pt, d, prm):
     return 0.5 * (GL + GR) - V_f * dis
 
 
-def residual(Qp, geo, prm, visc=None):
+def residual(Qp, geo, prm, visc=None, dyn=None):
     """R = RHS / V on the interior, for a padded state whose ghosts are
     filled; dQ/dt = -R (eq. spatial_discret with unit index spacing).
-    visc: held viscosities (see point_terms)."""
+    visc, dyn: held viscosities and dynamic coefficients (see point_terms)."""
     axis_node = prm["bc"][2] == "axis_node"
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-        pt = point_terms(Qp, geo, prm, visc)
+        pt = point_terms(Qp, geo, prm, visc, dyn)
         rhs = 0.0
         for d in range(3):
             F = face_fluxes(pt, d, prm)
@@ -638,15 +787,16 @@ def jameson_rk(Q0, resid, dt, alpha):
 
 
 def held_state(Q, geo, prm, inflow=None):
-    """Schedule "step" (L1, L2): the padded Q^n with its ghosts filled, and
-    its viscosities (mu, mu_t) on region one (None when inviscid)."""
+    """Schedule "step" (L1, L2, D8): the padded Q^n with its ghosts filled,
+    its viscosities (mu, mu_t) on region one and its dynamic-model
+    coefficients (None when inviscid / not dynamic)."""
     Hp = pad_state(np.asarray(Q))
     fill_ghosts(Hp, geo, prm, inflow)
     if prm["visc_coef"] == 0.0:
-        return Hp, None
+        return Hp, None, None
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
         pt = point_terms(Hp, geo, prm)
-    return Hp, (pt["mu"], pt["mu_t"])
+    return Hp, (pt["mu"], pt["mu_t"]), pt["dyn"]
 
 
 def rk5_step(Q, geo, prm, inflow=None, dt=None):
@@ -655,12 +805,12 @@ def rk5_step(Q, geo, prm, inflow=None, dt=None):
     if dt is None:
         dt = time_step(Q, geo, prm)
     if prm.get("schedule", "stage") == "step":
-        Hp, visc = held_state(Q, geo, prm, inflow)
+        Hp, visc, dyn = held_state(Q, geo, prm, inflow)
 
         def resid(q):
             Qp = pad_state(q)
             fill_ghosts(Qp, geo, prm, inflow, held=Hp)
-            return residual(Qp, geo, prm, visc)
+            return residual(Qp, geo, prm, visc, dyn)
     else:
         def resid(q):
             return evaluate(q, geo, prm, inflow)

@@ -26,6 +26,7 @@ FIELD_JET_IN = {"u": 21, "v": 22, "w": 23, "rho": 24, "p": 25}
 FIELD_COTANGENT = 31      # cotangents (output-side seeds of adjoint checks)
 FIELD_DIRECTION = 32      # perturbation directions (input side)
 FIELD_DIRECTION_IN = 33   # perturbation directions of the inflow data
+FIELD_MODES = 41          # phases of the multi-mode box velocity
 
 
 def conserved(rho, u, v, w, p, gamma=GAMMA):
@@ -177,3 +178,32 @@ def uniform_state(shape, prim, gamma=GAMMA, device="cpu"):
     """A uniform state (free stream) with primitives prim = (rho,u,v,w,p)."""
     f = [torch.full(shape, float(c), dtype=torch.float64, device=device) for c in prim]
     return conserved(*f, gamma=gamma)
+
+
+# ----------------------------------------------------------------------------
+# periodic box with a multi-mode velocity field
+# ----------------------------------------------------------------------------
+def modes_box_state(xyz, seed=1, kmax=3, amp=0.1, slope=1.0, tamp=0.05, rho=1.0,
+                    p=1.0 / GAMMA, gamma=GAMMA):
+    """u_c = sum over integer wave vectors 0 < |k|_inf <= kmax of
+    amp |k|^(-2 slope) cos(k . x + phi_{k,c}), seeded phases phi; uniform
+    density; pressure p (1 + s), s the same sum with amplitude `tamp` and
+    its own phases.  A field with an energy spectrum decaying with |k|
+    (dynamic SGS-model checks: random single-scale noise makes the model's
+    averages vanish)."""
+    x, y, z = xyz[0], xyz[1], xyz[2]
+    rng_idx = 0
+    f = [torch.zeros_like(x) for _ in range(4)]
+    ks = [(a, b, c) for a in range(-kmax, kmax + 1) for b in range(-kmax, kmax + 1)
+          for c in range(-kmax, kmax + 1) if (a, b, c) != (0, 0, 0)]
+    idx = torch.arange(4 * len(ks), dtype=torch.int64)
+    phases = 2.0 * math.pi * rng.uniform(seed, FIELD_MODES, idx)
+    for (a, b, c) in ks:
+        k2 = a * a + b * b + c * c
+        arg = a * x + b * y + c * z
+        for comp in range(4):
+            scale = amp if comp < 3 else tamp
+            f[comp] = f[comp] + scale * k2 ** (-slope) * torch.cos(arg + float(phases[rng_idx]))
+            rng_idx += 1
+    r = torch.full_like(x, rho)
+    return conserved(r, f[0], f[1], f[2], p * (1.0 + f[3]), gamma)

@@ -62,6 +62,16 @@ def box_problem(n=32, seed=1, Cs=0.148, noise=1e-4, shape=None):
                 params=box_params(L, Cs=Cs))
 
 
+def modes_box_problem(n=32, seed=1, kmax=3, amp=0.1, visc_coef=1e-3):
+    """Periodic box with the multi-mode velocity field and the dynamic SGS
+    model (a state on which its averaged coefficients are positive)."""
+    L = 2.0 * math.pi
+    xyz = mesh.box_coords(n, L)
+    Q = flow.modes_box_state(xyz, seed=seed, kmax=kmax, amp=amp)
+    return dict(name=f"modes{n}", xyz=xyz, Q=Q, inflow=None,
+                params=box_params(L, sgs_model=3, visc_coef=visc_coef))
+
+
 def jet_grid(nx, nr, nth, axis_node=False):
     """1-D maps of the jet mesh; axis_node puts the radial row j = 0 on the
     axis (r = 0) instead of at r = 0.005 D."""

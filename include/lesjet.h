@@ -113,8 +113,23 @@ enum les_bc {
  *   VREMAN       mu_sgs = rho c sqrt(B_beta / (alpha_ij alpha_ij)), c = 2.5 Cs^2,
  *                alpha_ij = d u_j / d x_i, beta_ij = Delta^2 alpha_mi alpha_mj,
  *                B_beta = b11 b22 - b12^2 + b11 b33 - b13^2 + b22 b33 - b23^2,
- *                zero where alpha_ij alpha_ij = 0 (or B_beta <= 0 by rounding). */
-enum les_sgs { LES_SGS_NONE = 0, LES_SGS_SMAGORINSKY = 1, LES_SGS_VREMAN = 2 };
+ *                zero where alpha_ij alpha_ij = 0 (or B_beta <= 0 by rounding);
+ *   DYNAMIC      (subsection "Dynamic Smagorinsky Model") mu_sgs = rho C_ds Delta^2 |S|
+ *                plus the isotropic stress sigma_kk = 2 C_I rho Delta^2 |S|^2
+ *                (sigma_kk / 3 added to the pressure of the momentum and energy
+ *                fluxes) and Pr_sgs from the model; C_I, C_ds, Pr_sgs are global
+ *                volume averages over the interior computed with the separable
+ *                (1/4, 1/2, 1/4) test filter and Delta_hat = 2 Delta before
+ *                every residual (LES_SCHEDULE_STEP: once per step); C_I, C_ds
+ *                below zero are taken as zero, Pr_sgs falls back to the static
+ *                value when not a positive number.  Cs is not used.  Holds 15
+ *                FP64 scratch variables of the padded layout. */
+enum les_sgs {
+  LES_SGS_NONE = 0,
+  LES_SGS_SMAGORINSKY = 1,
+  LES_SGS_VREMAN = 2,
+  LES_SGS_DYNAMIC = 3
+};
 
 typedef struct les_params {
   int32_t nx, nr, nth;        /* interior points along xi, eta, zeta (each >= 5) */
@@ -201,6 +216,15 @@ int les_residual(les_ctx* c, void* Q, void* R, void* stream);
  * a face pass): simple indexing, several times the memory traffic.  For
  * validating the fused kernel on meshes the CPU oracle cannot handle. */
 int les_residual_reference(les_ctx* c, void* Q, void* R, void* stream);
+
+/* Coefficients of the dynamic SGS model (LES_SGS_DYNAMIC; subsection
+ * "Dynamic Smagorinsky Model") for the state Q (device, padded, storage
+ * type; its ghosts are filled in place): coef (host, 6 doubles) receives
+ * C_I, C_ds and Pr_sgs as computed (Pr_sgs NaN when its denominator is 0),
+ * then the values the residual uses (C_I and C_ds clipped at 0, Pr_sgs or
+ * its static fallback).  Synchronises `stream`.  LES_EINVAL when the
+ * context uses another SGS model. */
+int les_dynamic_coefficients(les_ctx* c, void* Q, double* coef, void* stream);
 
 /* Advance Qn (device, FP64, padded, 5 variables) by `nsteps` Jameson RK5
  * steps (section "Time Marching Method"):

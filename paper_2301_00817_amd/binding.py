@@ -19,7 +19,7 @@ LES_FP64, LES_FP32_STORAGE = 0, 1
 LES_SCHEDULE_STAGE, LES_SCHEDULE_STEP = 0, 1
 SCHEDULE = {"stage": 0, "step": 1}
 BC = {"periodic": 0, "axis": 1, "inflow": 2, "outflow": 3, "farfield": 4, "axis_node": 5}
-SGS = {0: 0, 1: 1, 2: 2, "none": 0, "smagorinsky": 1, "vreman": 2}
+SGS = {0: 0, 1: 1, 2: 2, 3: 3, "none": 0, "smagorinsky": 1, "vreman": 2, "dynamic": 3}
 STATUS = {0: "LES_OK", -1: "LES_EINVAL", -2: "LES_ENOMEM", -3: "LES_EHIP",
           -4: "LES_ENONFINITE", -5: "LES_ESTATE", -6: "LES_EUNSUPPORTED"}
 
@@ -85,6 +85,7 @@ def _load():
         "les_fill_ghosts": ([vp, vp, vp], ctypes.c_int),
         "les_residual": ([vp, vp, vp, vp], ctypes.c_int),
         "les_residual_reference": ([vp, vp, vp, vp], ctypes.c_int),
+        "les_dynamic_coefficients": ([vp, vp, P(dbl * 6), vp], ctypes.c_int),
         "les_rk5_step": ([vp, vp, i32, dbl, vp, vp], ctypes.c_int),
         "les_residual_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "les_rk5_step_vjp": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
@@ -105,6 +106,7 @@ def _load():
 _lib = _load()
 EXPORTS = ("les_validate", "les_layout", "les_device_bytes", "les_init_grid", "les_metrics",
            "les_set_inflow", "les_fill_ghosts", "les_residual", "les_residual_reference",
+           "les_dynamic_coefficients",
            "les_rk5_step", "les_residual_vjp", "les_rk5_step_vjp", "les_diagnostics", "les_profile",
            "les_profile_read", "les_query",
            "les_last_error", "les_free")
@@ -161,6 +163,13 @@ def les_residual(ctx, q_ptr, r_ptr, stream=0):
 
 def les_residual_reference(ctx, q_ptr, r_ptr, stream=0):
     return _check(_lib.les_residual_reference(ctx, q_ptr, r_ptr, stream), ctx)
+
+
+def les_dynamic_coefficients(ctx, q_ptr, stream=0):
+    """(C_I, C_ds, Pr_sgs) as computed and as used, a 6-tuple of floats."""
+    out = (ctypes.c_double * 6)()
+    _check(_lib.les_dynamic_coefficients(ctx, q_ptr, ctypes.byref(out), stream), ctx)
+    return tuple(out)
 
 
 def les_rk5_step(ctx, qn_ptr, nsteps, dt_fixed=0.0, dt_out_ptr=None, stream=0):

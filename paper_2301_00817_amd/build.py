@@ -21,7 +21,7 @@ LIB = os.path.join(LIBDIR, "liblesjet.so")
 ARCH = os.environ.get("LESJET_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "geometry.hip", "ghost.hip", "residual_ref.hip", "residual_fused.hip",
-           "rk.hip", "diag.hip", "adjoint.hip"]
+           "rk.hip", "diag.hip", "adjoint.hip", "dynamic.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

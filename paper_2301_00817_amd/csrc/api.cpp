@@ -29,6 +29,9 @@ struct les_ctx {
   void* stage[3] = {nullptr, nullptr, nullptr};   // RK stage states (storage type; the
                                                  // third for FP32 with held boundary values)
   void* visc = nullptr;        // held mu + mu_sgs and conductivity (2 padded variables)
+  double* dyn_scr = nullptr;   // dynamic SGS model: scratch (DYN_SCRATCH_VARS variables, FP64),
+  double* dyn_part = nullptr;  // per-block sums
+  double* dyn = nullptr;       // and coefficients (DYN_COEF_DOUBLES)
   void* R = nullptr;           // residual buffer (storage type)
   void* PT = nullptr;          // point-quantity scratch of the two-pass residual
   double* part = nullptr;      // per-block partial sums of the diagnostics
@@ -130,8 +133,12 @@ static int validate(const les_params* p, std::string& why) {
   }
   if (b[1] == LES_BC_OUTFLOW && !finite_pos(p->p_exit)) { why = "p_exit must be > 0"; return LES_EINVAL; }
   if (p->sgs_model != LES_SGS_NONE && p->sgs_model != LES_SGS_SMAGORINSKY &&
-      p->sgs_model != LES_SGS_VREMAN) { why = "unknown sgs_model"; return LES_EINVAL; }
-  if (p->sgs_model != LES_SGS_NONE && p->visc_coef == 0.0 && p->Cs != 0.0) {
+      p->sgs_model != LES_SGS_VREMAN && p->sgs_model != LES_SGS_DYNAMIC) {
+    why = "unknown sgs_model";
+    return LES_EINVAL;
+  }
+  if (p->sgs_model != LES_SGS_NONE && p->visc_coef == 0.0 &&
+      (p->Cs != 0.0 || p->sgs_model == LES_SGS_DYNAMIC)) {
     why = "an SGS model needs visc_coef > 0 (mu_sgs is in units of the jet viscosity)";
     return LES_EINVAL;
   }
@@ -173,10 +180,12 @@ static Phys<T> make_phys(const les_params* p) {
   ph.suth = (T)p->suth_S;
   ph.suth1 = (T)(1.0 + p->suth_S);
   ph.viscous = p->visc_coef != 0.0;
-  ph.sgs = ph.viscous && p->Cs != 0.0 ? p->sgs_model : 0;
+  // the dynamic model takes no constant; its coefficients are set per launch
+  ph.sgs = ph.viscous && (p->Cs != 0.0 || p->sgs_model == LES_SGS_DYNAMIC) ? p->sgs_model : 0;
   // Vreman's constant is c = 2.5 Cs^2
   const double c = p->sgs_model == LES_SGS_VREMAN ? 2.5 * p->Cs * p->Cs : p->Cs * p->Cs;
-  ph.sgs_coef = ph.sgs ? (T)(c / p->visc_coef) : T(0);
+  ph.sgs_coef = ph.sgs && ph.sgs != LES_SGS_DYNAMIC ? (T)(c / p->visc_coef) : T(0);
+  ph.iso_coef = T(0);
   ph.k2 = (T)p->k2;
   ph.k4 = (T)p->k4;
   ph.axis_node = p->bc[2] == LES_BC_AXIS_NODE;
@@ -194,12 +203,14 @@ static size_t storage_size(const les_params* p) {
 
 static void free_all(les_ctx* c) {
   void* ptrs[] = {c->coords, c->M, c->inflow, c->stage[0], c->stage[1], c->stage[2], c->visc,
-                  c->R, c->PT, c->part, c->adj, c->adj_stage, c->maxbits, c->dt, c->flag};
+                  c->dyn_scr, c->dyn_part, c->dyn, c->R, c->PT, c->part, c->adj, c->adj_stage,
+                  c->maxbits, c->dt, c->flag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   c->coords = nullptr; c->M = nullptr; c->inflow = nullptr;
   c->stage[0] = c->stage[1] = c->stage[2] = nullptr;
   c->visc = nullptr;
+  c->dyn_scr = nullptr; c->dyn_part = nullptr; c->dyn = nullptr;
   c->R = nullptr; c->PT = nullptr; c->part = nullptr;
   c->adj = nullptr; c->adj_stage = nullptr;
   c->maxbits = nullptr; c->dt = nullptr; c->flag = nullptr;
@@ -263,6 +274,8 @@ int les_device_bytes(const les_params* p, size_t* bytes) {
   // variables when it is used); the per-step schedule adds the two held
   // viscosities and, in FP32, a third stage state
   size_t vars = 10 + 5 + 5;
+  if (p->sgs_model == LES_SGS_DYNAMIC && p->visc_coef != 0.0)
+    vars += (size_t)DYN_SCRATCH_VARS * sizeof(double) / ts;
   if (p->schedule == LES_SCHEDULE_STEP) {
     if (p->visc_coef != 0.0) vars += 2;
     if (p->precision == LES_FP32_STORAGE) vars += 5;
@@ -381,29 +394,96 @@ const Phys<double>& phys<double>(les_ctx* c) { return c->ph64; }
 template <>
 const Phys<float>& phys<float>(les_ctx* c) { return c->ph32; }
 
+static bool dynamic_model(const les_ctx* c) { return c->ph64.sgs == LES_SGS_DYNAMIC; }
+
+// Buffers of the dynamic model (allocated on first use).
+static int dynamic_ready(les_ctx* c) {
+  int r = dalloc(c, (void**)&c->dyn_scr, (size_t)DYN_SCRATCH_VARS * c->g.vs * sizeof(double),
+                 "dynamic-model scratch");
+  if (r == LES_OK)
+    r = dalloc(c, (void**)&c->dyn_part, (size_t)7 * dyn_blocks(c->g) * sizeof(double),
+               "dynamic-model sums");
+  if (r == LES_OK) r = dalloc(c, (void**)&c->dyn, DYN_COEF_DOUBLES * sizeof(double), "dynamic coefficients");
+  return r;
+}
+
+// Coefficients of the dynamic model for the ghost-filled state Q into c->dyn.
+template <typename T>
+static hipError_t dynamic_coefs(les_ctx* c, const T* Q, hipStream_t s) {
+  return launch_dynamic<T>(Q, (const T*)c->M, c->g, c->p.gamma, c->p.visc_coef, c->p.Pr_sgs,
+                           c->dyn_scr, c->dyn_part, c->dyn, s);
+}
+
 // R(Q) into R_out (ghosts of Q filled first), fused kernel.
 template <typename T>
 static int residual_into(les_ctx* c, T* Q, T* R_out, hipStream_t s) {
+  if (dynamic_model(c)) {
+    const int r = dynamic_ready(c);
+    if (r != LES_OK) return r;
+  }
   hipError_t e = ghosts<T>(c, Q, s);
+  if (e == hipSuccess && dynamic_model(c)) e = dynamic_coefs<T>(c, Q, s);
   if (e == hipSuccess) {
     const long k = prof_begin(c, s);
     e = launch_fused<T>(Q, (const T*)c->M, c->g, phys<T>(c), c->kc, FUSED_EPI_R, R_out, nullptr,
-                        nullptr, 0.0, nullptr, c->ph64, nullptr, FUSED_LAG_NONE, nullptr, s);
+                        nullptr, 0.0, nullptr, c->ph64, nullptr, FUSED_LAG_NONE, nullptr, c->dyn,
+                        s);
     prof_end(c, k, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "residual kernel");
   return LES_OK;
 }
 
-// Same, with the two-pass reference kernels.
+// Same, with the two-pass reference kernels (the dynamic coefficients are
+// read back to the host for them: this path synchronises).
 template <typename T>
 static int residual_ref_into(les_ctx* c, T* Q, T* R_out, hipStream_t s) {
   int r = dalloc(c, &c->PT, (size_t)21 * c->g.vs * sizeof(T), "point scratch");
+  if (r == LES_OK && dynamic_model(c)) r = dynamic_ready(c);
   if (r != LES_OK) return r;
   hipError_t e = ghosts<T>(c, Q, s);
+  Phys<T> ph = phys<T>(c);
+  if (e == hipSuccess && dynamic_model(c)) {
+    double d[3] = {0.0, 0.0, 0.0};
+    e = dynamic_coefs<T>(c, Q, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d, c->dyn, sizeof(d), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    ph.sgs_coef = (T)d[0];
+    ph.Prs_inv = (T)d[1];
+    ph.iso_coef = (T)d[2];
+  }
   if (e == hipSuccess)
-    e = launch_residual_ref<T>(Q, (const T*)c->M, c->g, phys<T>(c), (T*)c->PT, R_out, s);
+    e = launch_residual_ref<T>(Q, (const T*)c->M, c->g, ph, (T*)c->PT, R_out, s);
   if (e != hipSuccess) return hip_fail(c, e, "reference residual kernels");
+  return LES_OK;
+}
+
+int les_dynamic_coefficients(les_ctx* c, void* Q, double* coef, void* stream) {
+  int r = ready(c);
+  if (r != LES_OK) return r;
+  if (!Q || !coef) return fail(c, LES_EINVAL, "Q or coef is NULL");
+  if (!dynamic_model(c)) return fail(c, LES_EINVAL, "the context does not use the dynamic SGS model");
+  r = dynamic_ready(c);
+  if (r != LES_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (c->p.precision == LES_FP32_STORAGE) {
+    e = ghosts<float>(c, (float*)Q, s);
+    if (e == hipSuccess) e = dynamic_coefs<float>(c, (const float*)Q, s);
+  } else {
+    e = ghosts<double>(c, (double*)Q, s);
+    if (e == hipSuccess) e = dynamic_coefs<double>(c, (const double*)Q, s);
+  }
+  double d[DYN_COEF_DOUBLES];
+  if (e == hipSuccess) e = hipMemcpyAsync(d, c->dyn, sizeof(d), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "dynamic-model kernels");
+  coef[0] = d[3];                         // C_I
+  coef[1] = d[4];                         // C_ds
+  coef[2] = d[5];                         // Pr_sgs as computed
+  coef[3] = 1.5 * d[2];                   // C_I used
+  coef[4] = d[0] * c->p.visc_coef;        // C_ds used
+  coef[5] = 1.0 / d[1];                   // Pr_sgs used
   return LES_OK;
 }
 
@@ -452,6 +532,7 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
   int r = LES_OK;
   for (int b = 0; b < nbuf && r == LES_OK; ++b) r = dalloc(c, &c->stage[b], fb, "stage state");
   if (r == LES_OK && lagv) r = dalloc(c, &c->visc, (size_t)2 * c->g.vs * sizeof(T), "held viscosities");
+  if (r == LES_OK && dynamic_model(c)) r = dynamic_ready(c);
   if (r != LES_OK) return r;
   const bool cfl = dt_fixed <= 0.0;
   T* B[3] = {(T*)c->stage[0], (T*)c->stage[1], (T*)c->stage[2]};
@@ -477,6 +558,9 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
     T* src = cur;
     for (int l = 0; l < 5 && e == hipSuccess; ++l) {
       e = l > 0 && held_sched ? ghosts_held<T>(c, src, held, s) : ghosts<T>(c, src, s);
+      // dynamic model: coefficients of this stage's state (held: of Q^n)
+      if (e == hipSuccess && dynamic_model(c) && (l == 0 || !held_sched))
+        e = dynamic_coefs<T>(c, src, s);
       if (e != hipSuccess) break;
       // destination: a buffer other than the source and, while later stages
       // still copy from it, other than the held state
@@ -494,7 +578,7 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
       const int lag = !lagv ? FUSED_LAG_NONE : (l == 0 ? FUSED_LAG_WRITE : FUSED_LAG_READ);
       const long k = prof_begin(c, s);
       e = launch_fused<T>(src, M, c->g, phys<T>(c), c->kc, epi, dst, Qn, q64, c->p.rk_alpha[l],
-                          c->dt, c->ph64, c->maxbits, lag, (T*)c->visc, s);
+                          c->dt, c->ph64, c->maxbits, lag, (T*)c->visc, c->dyn, s);
       prof_end(c, k, s);
       src = dst;
     }
@@ -567,6 +651,8 @@ static int adjoint_ready(les_ctx* c) {
     return fail(c, LES_EUNSUPPORTED, "the adjoint is available for the FP64 precision only");
   if (c->p.bc[2] == LES_BC_AXIS_NODE)
     return fail(c, LES_EUNSUPPORTED, "the adjoint does not cover the axis_node centerline");
+  if (dynamic_model(c))
+    return fail(c, LES_EUNSUPPORTED, "the adjoint does not cover the dynamic SGS model");
   return LES_OK;
 }
 
@@ -611,7 +697,7 @@ int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, 
     if (e == hipSuccess)
       e = launch_fused<double>(X[l - 1], (const double*)c->M, c->g, c->ph64, c->kc, FUSED_EPI_RK,
                                X[l], Qn, nullptr, al[l - 1], c->dt, c->ph64, c->maxbits,
-                               FUSED_LAG_NONE, nullptr, s);
+                               FUSED_LAG_NONE, nullptr, nullptr, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "rk5 adjoint forward kernels");
   // reverse: b5 = Qbar^(n+1); b(l-1) = -alpha_l dt J(Q^(l-1))^T b(l);

@@ -44,11 +44,13 @@ struct Phys {
   T Pr_inv, Prs_inv;      // 1/Pr, 1/Pr_sgs
   T Cv;                   // visc_coef = M/Re
   T suth, suth1;          // S, 1 + S (Sutherland)
-  T sgs_coef;             // Smagorinsky Cs^2 / Cv, Vreman 2.5 Cs^2 / Cv
-                          // (eddy viscosity in jet-viscosity units)
+  T sgs_coef;             // Smagorinsky Cs^2 / Cv, Vreman 2.5 Cs^2 / Cv, dynamic
+                          // C_ds / Cv (eddy viscosity in jet-viscosity units)
+  T iso_coef;             // dynamic: (2/3) C_I (isotropic SGS stress), else 0
   T k2, k4;
   int viscous;            // Cv != 0
-  int sgs;                // 0 none, 1 Smagorinsky, 2 Vreman
+  int sgs;                // 0 none, 1 Smagorinsky, 2 Vreman, 3 dynamic (sgs_coef,
+                          // Prs_inv and iso_coef set per launch from the device)
   int axis_node;          // eta- is a centerline through the mesh nodes j = 0
   int phys_face[3][2];    // face -1/2 / n-1/2 along d is a physical boundary
 };

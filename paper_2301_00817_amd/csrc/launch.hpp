@@ -31,11 +31,25 @@ hipError_t launch_residual_ref(const T* Q, const T* M, const Grid& g, const Phys
 template <typename T>
 int fused_chunk(const Grid& g, int num_cu);
 
+// dyn: coefficients of the dynamic SGS model (device, see launch_dynamic),
+// read when ph.sgs == 3; may be NULL otherwise.
 template <typename T>
 hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, int kc, int epi,
                         T* out, const double* Q0, double* Q64, double alpha, const double* dt,
                         const Phys<double>& ph64, unsigned long long* maxbits, int lag, T* visc,
-                        hipStream_t s);
+                        const double* dyn, hipStream_t s);
+
+// Dynamic Smagorinsky coefficients of the ghost-filled state Q: scratch SC
+// (DYN_SCRATCH_VARS padded FP64 variables), part (7 doubles per block of
+// dyn_blocks(g)), dyn (DYN_COEF_DOUBLES): [0] C_ds+ / Cv, [1] 1 / Pr_sgs,
+// [2] (2/3) C_I+, [3..5] C_I, C_ds, Pr_sgs as computed, [6..12] the sums.
+constexpr int DYN_SCRATCH_VARS = 15;
+constexpr int DYN_COEF_DOUBLES = 16;
+int dyn_blocks(const Grid& g);
+template <typename T>
+hipError_t launch_dynamic(const T* Q, const T* M, const Grid& g, double gamma, double Cv,
+                          double Pr_static, double* SC, double* part, double* dyn,
+                          hipStream_t s);
 
 enum { FUSED_EPI_R = 0, FUSED_EPI_RK = 1, FUSED_EPI_RK_LAST = 2 };
 // viscosity schedule of the stage kernel (same values as LAG_* of the

@@ -194,7 +194,9 @@ struct PointOut {
 // also returned for holding (LAG_WRITE), or taken from held values (LAG_READ).
 enum { LAG_NONE = 0, LAG_WRITE = 1, LAG_READ = 2 };
 
-template <typename T, int LAG = LAG_NONE>
+// DYN: the dynamic SGS model's terms are compiled in (used when ph.sgs == 3);
+// a separate instance so that the other models carry none of them.
+template <typename T, int LAG = LAG_NONE, bool DYN = false>
 __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phys<T>& ph,
                                                  PointOut<T>& out) {
   Prim<T> s;
@@ -244,12 +246,40 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
       } else if (ph.sgs == 2) {                               // Vreman
         const T delta = tcbrt(tabs(in.V));
         mut = s.rho * ph.sgs_coef * delta * delta * vreman_ratio(g);
+      } else if (DYN && ph.sgs == 3) {                        // dynamic: C_ds Delta^2 |S|
+        T s2 = T(0);
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            const T sij = T(0.5) * (g[i][j] + g[j][i]);
+            s2 += sij * sij;
+          }
+        const T delta = tcbrt(tabs(in.V));
+        mut = s.rho * ph.sgs_coef * delta * delta * tsqrt(T(2) * s2);
       }
       mt = mu + mut;
       kap = (mu * ph.Pr_inv + mut * ph.Prs_inv) * ph.igm1;
       if (LAG == LAG_WRITE) {
         out.mt = mt;
         out.kap = kap;
+      }
+    }
+    if (DYN && ph.sgs == 3) {
+      // isotropic SGS stress of the dynamic model: sigma_kk / 3 =
+      // (2/3) C_I rho Delta^2 |S|^2 acts as a pressure in the momentum and
+      // energy point fluxes (stage |S|, coefficient of the launch)
+      T s2 = T(0);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          const T sij = T(0.5) * (g[i][j] + g[j][i]);
+          s2 += sij * sij;
+        }
+      const T delta = tcbrt(tabs(in.V));
+      const T psgs = ph.iso_coef * s.rho * delta * delta * (T(2) * s2);
+      for (int d = 0; d < 3; ++d) {
+        out.G[d][1] += psgs * in.S[d][0];
+        out.G[d][2] += psgs * in.S[d][1];
+        out.G[d][3] += psgs * in.S[d][2];
+        out.G[d][4] += psgs * Uc[d];
       }
     }
     const T div = g[0][0] + g[1][1] + g[2][2];

@@ -140,12 +140,18 @@ template <> struct FusedOcc<float> { static constexpr int waves = 4; };
 // padded variables; LAG_READ takes them from there).  The tiling is the same
 // in every stage, so the points read are those written; points shared by
 // two blocks are written twice with the same value.
-template <typename T, int EPI, bool AXIS, int LAG>
+template <typename T, int EPI, bool AXIS, int LAG, bool DYN>
 __global__ void __launch_bounds__(Tile<T>::X * Tile<T>::Y, FusedOcc<T>::waves)
-k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, int kc,
+k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_arg, int kc,
         TileMap tm, T* out, const double* Q0, double* Q64, double alpha,
         const double* __restrict__ dtp, Phys<double> ph64, unsigned long long* __restrict__ maxbits,
-        T* __restrict__ visc) {
+        T* __restrict__ visc, const double* __restrict__ dyn) {
+  Phys<T> ph = ph_arg;
+  if (DYN) {   // dynamic model: coefficients of this state, from the device
+    ph.sgs_coef = (T)dyn[0];
+    ph.Prs_inv = (T)dyn[1];
+    ph.iso_coef = (T)dyn[2];
+  }
   constexpr int FB_X = Tile<T>::X;              // threads along i (ring-1 columns)
   constexpr int FB_Y = Tile<T>::Y;              // threads along j
   constexpr int FT_X = FB_X - 2;                // interior outputs along i
@@ -309,7 +315,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph, 
       for (int c = 0; c < 3; ++c) in.S[d][c] = met[3 * d + c];
     in.V = met[9];
     if (LAG == LAG_READ) { in.mt = lag[0]; in.kap = lag[1]; }
-    point_quantities<T, LAG>(in, ph, po);
+    point_quantities<T, LAG, DYN>(in, ph, po);
     if (LAG == LAG_WRITE && col_ok && ph.viscous) {
       const int o = g.at(i, j, kk);
       visc[o] = po.mt;
@@ -544,7 +550,8 @@ template <typename T>
 hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph, int kc, int epi,
                         T* out, const double* Q0, double* Q64, double alpha, const double* dt,
                         const Phys<double>& ph64, unsigned long long* maxbits, int lag, T* visc,
-                        hipStream_t s) {
+                        const double* dyn, hipStream_t s) {
+  if (ph.sgs == 3 && !dyn) return hipErrorInvalidValue;
   // instances: LAG_NONE with every epilogue, LAG_WRITE with EPI_RK (stage 1),
   // LAG_READ with EPI_RK and EPI_RK_LAST (stages 2-5)
   if (lag != LAG_NONE && (!visc || epi == EPI_R || (lag == LAG_WRITE && epi != EPI_RK)))
@@ -558,9 +565,15 @@ hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph
   tm.per_xcd = (int)((ntiles + NXCD - 1) / NXCD);
   const dim3 grid((unsigned)(tm.per_xcd * NXCD));
   const dim3 block(Tile<T>::X, Tile<T>::Y, 1);
-#define LESJET_FUSED(E, A, L)                                                                   \
-  hipLaunchKernelGGL((k_fused<T, E, A, L>), grid, block, 0, s, Q, M, g, ph, kc, tm, out, Q0, Q64, \
-                     alpha, dt, ph64, maxbits, visc)
+#define LESJET_FUSED(E, A, L)                                                          \
+  do {                                                                                 \
+    if (ph.sgs == 3)                                                                   \
+      hipLaunchKernelGGL((k_fused<T, E, A, L, true>), grid, block, 0, s, Q, M, g, ph, kc, tm, \
+                         out, Q0, Q64, alpha, dt, ph64, maxbits, visc, dyn);           \
+    else                                                                               \
+      hipLaunchKernelGGL((k_fused<T, E, A, L, false>), grid, block, 0, s, Q, M, g, ph, kc, tm, \
+                         out, Q0, Q64, alpha, dt, ph64, maxbits, visc, dyn);           \
+  } while (0)
 #define LESJET_FUSED_EPI(A)                                                        \
   if (lag == LAG_WRITE) LESJET_FUSED(EPI_RK, A, LAG_WRITE);                        \
   else if (lag == LAG_READ) {                                                      \
@@ -584,10 +597,11 @@ template int fused_chunk<float>(const Grid&, int);
 template hipError_t launch_fused<double>(const double*, const double*, const Grid&,
                                          const Phys<double>&, int, int, double*, const double*,
                                          double*, double, const double*, const Phys<double>&,
-                                         unsigned long long*, int, double*, hipStream_t);
+                                         unsigned long long*, int, double*, const double*,
+                                         hipStream_t);
 template hipError_t launch_fused<float>(const float*, const float*, const Grid&, const Phys<float>&,
                                         int, int, float*, const double*, double*, double,
                                         const double*, const Phys<double>&, unsigned long long*,
-                                        int, float*, hipStream_t);
+                                        int, float*, const double*, hipStream_t);
 
 }  // namespace lesjet

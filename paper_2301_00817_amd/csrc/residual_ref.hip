@@ -45,7 +45,7 @@ __global__ void k_point_pass(const T* __restrict__ Q, const T* __restrict__ M, G
   }
   in.V = M[9LL * g.vs + o];
   PointOut<T> out;
-  point_quantities(in, ph, out);
+  point_quantities<T, LAG_NONE, true>(in, ph, out);
   if (ph.axis_node && j == 0)          // centerline through the nodes: no eta point flux
     for (int c = 0; c < 5; ++c) out.G[1][c] = T(0);
 #pragma unroll

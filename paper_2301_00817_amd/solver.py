@@ -44,7 +44,7 @@ class Solver:
         self.metrics64 = None
         out = None
         if keep_metrics:
-            out = torch.empty((10,) + self.dims, dtype=torch.float64, device=self.device)
+            out = torch.zeros((10,) + self.dims, dtype=torch.float64, device=self.device)
         B.les_metrics(self.ctx, out.data_ptr() if out is not None else None, _stream(self.device))
         self.metrics64 = out
         if inflow is not None:
@@ -91,6 +91,13 @@ class Solver:
             R = self.field(5, fill=float("nan"))
         B.les_residual_reference(self.ctx, Qp.data_ptr(), R.data_ptr(), _stream(self.device))
         return R
+
+    def dynamic_coefficients(self, Qp):
+        """Dynamic SGS model coefficients of the padded state Qp (storage
+        type; ghosts filled in place): (C_I, C_ds, Pr_sgs) as computed, then
+        as used."""
+        assert Qp.dtype == self.dtype and tuple(Qp.shape) == (5,) + self.dims and Qp.is_contiguous()
+        return B.les_dynamic_coefficients(self.ctx, Qp.data_ptr(), _stream(self.device))
 
     def rk5_step(self, Qn, nsteps=1, dt=0.0, dt_out=None):
         """Advance the padded FP64 state Qn in place; returns the per-step dt

@@ -20,8 +20,9 @@ Phys<double> make_phys(int sgs) {
   ph.Pr_inv = 1.0 / 0.72; ph.Prs_inv = 1.0 / 0.9;
   ph.Cv = 0.02; ph.suth = 110.4 / 288.15; ph.suth1 = 1.0 + ph.suth;
   ph.sgs_coef = (sgs == 2 ? 2.5 : 1.0) * 0.148 * 0.148 / ph.Cv;
+  ph.iso_coef = 0.0;
   ph.k2 = 0.25; ph.k4 = 0.016;
-  ph.viscous = 1; ph.sgs = sgs;
+  ph.viscous = 1; ph.sgs = sgs; ph.axis_node = 0;
   for (int d = 0; d < 3; ++d) ph.phys_face[d][0] = ph.phys_face[d][1] = 0;
   return ph;
 }

@@ -162,7 +162,7 @@ def test_free_stream_on_full_size_axis_mesh():
     R = s.interior(s.residual(s.pad(Q.cuda())))
     V = s.interior(s.metrics64[9:10])
     VR = float((R * V).abs().max())
-    Smax = float(s.metrics64[:9].abs().max())
+    Smax = float(s.interior(s.metrics64[:9]).abs().max())
     fscale = Smax * (prim[0] * 0.6 ** 2 + prim[4])
     assert torch.isfinite(R).all()
     assert VR <= 1e-12 * fscale

@@ -66,7 +66,7 @@ def test_fp32_free_stream():
     R = s.interior(s.residual(s.pad(Q.cuda().float()))).double()
     V = s.interior(s.metrics64[9:10])
     VR = float((R * V).abs().max())
-    fscale = float(s.metrics64[:9].abs().max()) * (0.6 ** 2 + prim[4])
+    fscale = float(s.interior(s.metrics64[:9]).abs().max()) * (0.6 ** 2 + prim[4])
     print(f"FP32 free stream: {VR / fscale:.3e}")
     assert VR <= 1e-5 * fscale
     s.close()

@@ -184,7 +184,7 @@ def test_free_stream_on_5p9M_jet_mesh():
     R = s.interior(s.residual(Qp))
     V = s.interior(s.metrics64[9:10])
     VR = float((R * V).abs().max())
-    Smax = float(s.metrics64[:9].abs().max())
+    Smax = float(s.interior(s.metrics64[:9]).abs().max())
     fscale = Smax * (prim[0] * 0.6 ** 2 + prim[4])
     assert VR <= 1e-12 * fscale
     s.close()

@@ -227,6 +227,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="jet5.9M")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--sgs", default=None, choices=["none", "smagorinsky", "vreman", "dynamic"],
+                    help="subgrid model (default: the workload's own)")
     ap.add_argument("--schedule", default="stage", choices=["stage", "step"],
                     help="update viscosities and boundary values every stage (default) or "
                          "once per step, as the paper's solver does")
@@ -269,7 +271,7 @@ def main():
         return
     from cases import problems
     kind = problems.CONFIGS[args.config]["kind"]
-    r = time_rk(args.config, args.precision, args.steps, args.warmup, dev, args.schedule)
+    r = time_rk(args.config, args.precision, args.steps, args.warmup, dev, args.schedule, args.sgs)
     nx, nr, nth = r["shape"]
     npts = nx * nr * nth
     prm = r["params"]
@@ -300,7 +302,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"jet mesh {nx}x{nr}x{nth} ({npts} points), {args.precision}, "
                                f"CFL {prm['cfl']}, RK5 steps"
-                               + ("" if prm.get("sgs_model", 1) else ", no SGS model")
+                               + {0: ", no SGS model", 1: "", 2: ", Vreman SGS model",
+                                  3: ", dynamic SGS model"}[prm.get("sgs_model", 1)]
                                + (", viscosities and boundary values updated once per step"
                                   if args.schedule == "step" else "")
                                if kind == "jet" else
@@ -314,7 +317,7 @@ def main():
     if not args.no_extras:
         other = "fp32" if args.precision == "fp64" else "fp64"
         print(f"[bench] same workload in {other}", file=sys.stderr, flush=True)
-        r2 = time_rk(args.config, other, args.steps, args.warmup, dev, args.schedule)
+        r2 = time_rk(args.config, other, args.steps, args.warmup, dev, args.schedule, args.sgs)
         v2 = npts * 5 * args.steps / r2["wall"] / 1e6
         fp32_v, fp64_v = (v2, value) if other == "fp32" else (value, v2)
         out["precision_forms"] = {"fp64": round(fp64_v, 2), "fp32": round(fp32_v, 2),
@@ -330,13 +333,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_rk(config, precision, steps, warmup, dev, schedule="stage"):
+SGS_MODELS = {"none": 0, "smagorinsky": 1, "vreman": 2, "dynamic": 3}
+
+
+def time_rk(config, precision, steps, warmup, dev, schedule="stage", sgs=None):
     """Wall time of `steps` RK5 steps (CFL dt) of a workload resident in HBM,
     with the stage kernel's launches timed by HIP events on its stream."""
     import torch
     from paper_2301_00817_amd.solver import Solver
     prm, xyz, fill, inflow = make_workload(config, dev)
     prm = dict(prm, schedule=schedule)
+    if sgs is not None:
+        prm["sgs_model"] = SGS_MODELS[sgs]
     s = Solver(prm, xyz, inflow, precision=precision, device=dev)
     del xyz
     torch.cuda.empty_cache()

@@ -91,24 +91,28 @@ __device__ __forceinline__ void strain(const double gu[3][3], double S[3][3], do
   Smag = sqrt(2.0 * s2);
 }
 
-// Separable 27-point filter of NF fields at o: along i, then j, then k,
-// each pass 0.25 lo + 0.5 mid + 0.25 hi; `val(o, f)` gives field f at o.
+// The 27-point product filter (weights FW[a] FW[b] FW[c], the separable
+// three-point filter along i, j and k) of NF fields at o, accumulated point
+// by point (few live registers); `val(o, v)` gives the fields at o.
 template <int NF, typename F>
 __device__ __forceinline__ void filter27(const Grid& g, int o, F val, double out[NF]) {
-  double zk[3][NF];
-  for (int dk = 0; dk < 3; ++dk) {
-    double yj[3][NF];
+  for (int f = 0; f < NF; ++f) out[f] = 0.0;
+  // few fields: unrolled (loads in flight together); many: rolled (registers)
+  constexpr int U = NF <= 5 ? 3 : 1;
+#pragma unroll U
+  for (int dk = 0; dk < 3; ++dk)
+#pragma unroll U
     for (int dj = 0; dj < 3; ++dj) {
+      const double wjk = FW[dk] * FW[dj];
       const int ob = o + (dk - 1) * g.plane + (dj - 1) * g.pitch;
-      double a[NF], b[NF], c[NF];
-      val(ob - 1, a);
-      val(ob, b);
-      val(ob + 1, c);
-      for (int f = 0; f < NF; ++f) yj[dj][f] = FW[0] * a[f] + FW[1] * b[f] + FW[2] * c[f];
+#pragma unroll
+      for (int di = 0; di < 3; ++di) {
+        double v[NF];
+        val(ob + di - 1, v);
+        const double w = wjk * FW[di];
+        for (int f = 0; f < NF; ++f) out[f] += w * v[f];
+      }
     }
-    for (int f = 0; f < NF; ++f) zk[dk][f] = FW[0] * yj[0][f] + FW[1] * yj[1][f] + FW[2] * yj[2][f];
-  }
-  for (int f = 0; f < NF; ++f) out[f] = FW[0] * zk[0][f] + FW[1] * zk[1][f] + FW[2] * zk[2][f];
 }
 
 template <typename T>

@@ -123,7 +123,8 @@ enum les_bc {
  *                every residual (LES_SCHEDULE_STEP: once per step); C_I, C_ds
  *                below zero are taken as zero, Pr_sgs falls back to the static
  *                value when not a positive number.  Cs is not used.  Holds 15
- *                FP64 scratch variables of the padded layout. */
+ *                FP64 scratch variables of the padded layout.  Not available
+ *                with LES_BC_AXIS_NODE (les_validate: LES_EUNSUPPORTED). */
 enum les_sgs {
   LES_SGS_NONE = 0,
   LES_SGS_SMAGORINSKY = 1,
@@ -154,7 +155,8 @@ typedef struct les_params {
 /* ---- host-only helpers (no device work; callable without a GPU) -------- */
 
 /* Validate `p` (sizes >= 5, consistent boundary kinds, finite positive
- * constants).  Returns LES_OK or LES_EINVAL. */
+ * constants).  Returns LES_OK, LES_EINVAL, or LES_EUNSUPPORTED for a valid
+ * combination this library does not provide. */
 int les_validate(const les_params* p);
 
 /* Padded layout for `p`: *pitch = row pitch in elements, dims[0..2] =

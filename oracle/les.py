@@ -605,6 +605,9 @@ def dynamic_coefficients(Qp, geo, prm):
     "Dynamic Smagorinsky Model"; readings D1-D6) from a padded state whose
     ghosts are filled.  Returns the raw ratios, the volume-weighted sums
     they come from, and the values used (C_I_eff, C_ds_eff, Pr_eff)."""
+    if prm["bc"][2] == "axis_node":
+        raise NotImplementedError("the dynamic model's test filter would average the axis "
+                                  "row, where J^-1 = 0 leaves the strain undefined")
     gamma = prm["gamma"]
     rho, u, v, w, p = primitives(Qp, gamma)
     T = gamma * p / rho

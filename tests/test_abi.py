@@ -127,7 +127,23 @@ def test_entry_points_reject_a_null_context(call):
 
 def test_validate_accepts_every_sgs_model():
     from paper_2301_00817_amd import binding as B
-    for m in (0, 1, 2, "none", "smagorinsky", "vreman"):
+    for m in (0, 1, 2, 3, "none", "smagorinsky", "vreman", "dynamic"):
         assert B.les_validate(_params(sgs_model=m)) == 0
-    with pytest.raises(B.LesError):
-        B.les_validate(_params(sgs_model=2, visc_coef=0.0))
+    for m in (2, 3):
+        with pytest.raises(B.LesError):
+            B.les_validate(_params(sgs_model=m, visc_coef=0.0))
+    # the dynamic model with nodes on the axis is a combination not provided
+    bc = ("inflow", "outflow", "axis_node", "farfield", "periodic", "periodic")
+    with pytest.raises(B.LesError) as e:
+        B.les_validate(_params(sgs_model=3, bc=bc))
+    assert e.value.code == B.LES_EUNSUPPORTED
+    assert B.les_validate(_params(sgs_model=1, bc=bc)) == 0
+
+
+def test_validate_accepts_both_schedules_and_rejects_others():
+    from paper_2301_00817_amd import binding as B
+    for sch in ("stage", "step", 0, 1):
+        assert B.les_validate(_params(schedule=sch)) == 0
+    with pytest.raises(B.LesError) as e:
+        B.les_validate(_params(schedule=5))
+    assert e.value.code == B.LES_EINVAL

@@ -47,12 +47,13 @@ __device__ __forceinline__ PrimD prim_at(const T* __restrict__ Q, const Grid& g,
   const double q0 = (double)Q[o], q1 = (double)Q[(long long)g.vs + o],
                q2 = (double)Q[2LL * g.vs + o], q3 = (double)Q[3LL * g.vs + o],
                q4 = (double)Q[4LL * g.vs + o];
+  const double ir = 1.0 / q0;          // one division per point
   s.rho = q0;
-  s.u = q1 / q0;
-  s.v = q2 / q0;
-  s.w = q3 / q0;
+  s.u = q1 * ir;
+  s.v = q2 * ir;
+  s.w = q3 * ir;
   s.p = (gamma - 1.0) * (q4 - 0.5 * q0 * (s.u * s.u + s.v * s.v + s.w * s.w));
-  s.T = gamma * s.p / q0;
+  s.T = gamma * s.p * ir;
   return s;
 }
 
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_sums(const T* __restrict__ Q,
       for (int c = 0; c < 3; ++c) v[6 + c] = s.rho * uu[c] * s.T;
     }, hP);
     const double hr = SC[(long long)DY_HR * g.vs + o];
+    const double ihr = 1.0 / hr;
     double hru[3];
     for (int c = 0; c < 3; ++c) hru[c] = SC[(long long)(DY_HRU + c) * g.vs + o];
     const double hrT = SC[(long long)DY_HRT * g.vs + o];
@@ -189,11 +191,12 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_sums(const T* __restrict__ Q,
     double dl[3][4];
     for (int d = 0; d < 3; ++d) {
       const int op = o + step[d], om = o - step[d];
-      const double rp = SC[(long long)DY_HR * g.vs + op], rm = SC[(long long)DY_HR * g.vs + om];
+      const double irp = 1.0 / SC[(long long)DY_HR * g.vs + op];
+      const double irm = 1.0 / SC[(long long)DY_HR * g.vs + om];
       for (int c = 0; c < 3; ++c)
-        dl[d][c] = 0.5 * (SC[(long long)(DY_HRU + c) * g.vs + op] / rp -
-                          SC[(long long)(DY_HRU + c) * g.vs + om] / rm);
-      dl[d][3] = 0.5 * (SC[(long long)DY_HRT * g.vs + op] / rp - SC[(long long)DY_HRT * g.vs + om] / rm);
+        dl[d][c] = 0.5 * (SC[(long long)(DY_HRU + c) * g.vs + op] * irp -
+                          SC[(long long)(DY_HRU + c) * g.vs + om] * irm);
+      dl[d][3] = 0.5 * (SC[(long long)DY_HRT * g.vs + op] * irp - SC[(long long)DY_HRT * g.vs + om] * irm);
     }
     const double V = (double)M[9LL * g.vs + o];
     const double iV = 1.0 / V;
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_sums(const T* __restrict__ Q,
     for (int q = 0; q < 6; ++q) {
       const int a = IJ[q][0], b = IJ[q][1];
       const double w = a == b ? 1.0 : 2.0;            // symmetric: off-diagonals twice
-      const double L = hP[q] - hru[a] * hru[b] / hr;
+      const double L = hP[q] - hru[a] * hru[b] * ihr;
       if (a == b) Lll += L;
       LS += w * L * S[a][b];
       hSS += w * hF[DY_FS + q] * S[a][b];
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_sums(const T* __restrict__ Q,
     double NP = 0.0, DP = 0.0;
     for (int m = 0; m < 3; ++m) {
       NP += D2 * hF[DY_FT + m] * gT[m] - Dh2 * hr * Shmag * gTh[m] * gT[m];
-      DP += (hP[6 + m] - hru[m] * hrT / hr) * gT[m];
+      DP += (hP[6 + m] - hru[m] * hrT * ihr) * gT[m];
     }
     term[0] = Lll;                                                     // N_I
     term[1] = 2.0 * Dh2 * hr * Shmag * Shmag - 2.0 * D2 * hS2;         // D_I

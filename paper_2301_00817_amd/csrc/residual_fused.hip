@@ -10,14 +10,14 @@
 //       ring-1 column, with in-plane neighbours from LDS and the kk-1, kk+1
 //       neighbours from the thread's own registers, and publishes the xi and
 //       eta ones in LDS,
-//   (c) forms the in-plane face fluxes of the interior columns from LDS and
-//       the zeta face kk-1/2 from registers (point quantities of plane kk-1
-//       are kept from the previous iteration), which completes R at plane
-//       kk-1.
-// Every point quantity of a ring-1 column is computed once per plane; the
-// in-plane faces are evaluated once from each side.  HBM traffic per
-// interior point and stage: Q (in), the 10 metric arrays, Q^(0) and the
-// output, the halos coming from L2.
+//   (c) evaluates the in-plane faces i - 1/2 and j - 1/2 of each column from
+//       LDS and publishes their fluxes; after a barrier each interior column
+//       takes its flux differences from LDS and forms the zeta face kk-1/2
+//       from registers (point quantities of plane kk-1 are kept from the
+//       previous iteration), which completes R at plane kk-1.
+// Every point quantity of a ring-1 column is computed once per plane, every
+// face flux once.  HBM traffic per interior point and stage: Q (in), the 10
+// metric arrays, Q^(0) and the output, the halos coming from L2.
 //
 // Epilogues: EPI_R writes R; EPI_RK writes Q^(l) = Q^(0) - alpha dt R
 // (accumulated in FP64, stored in the stage type); EPI_RK_LAST also writes

@@ -103,8 +103,11 @@ enum les_bc {
                              the caller's state is derived data: the ghost fill
                              of les_residual / les_rk5_step writes the mean into
                              it, and les_rk5_step returns it as the mean of the
-                             returned state's row 1.  Needs even nth; the
-                             adjoint entry points return LES_EUNSUPPORTED. */
+                             returned state's row 1.  Needs even nth.  The
+                             adjoints follow: the axis row's cotangent is zero
+                             (R does not depend on it), and les_rk5_step_vjp
+                             first moves the cotangent of the returned axis
+                             row to row 1 (the transpose of that mean). */
 };
 
 /* Subgrid-scale eddy viscosity (subsection "Subgrid Scale Modeling"), in
@@ -241,7 +244,8 @@ int les_dynamic_coefficients(les_ctx* c, void* Q, double* coef, void* stream);
 int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed,
                  double* dt_out, void* stream);
 
-/* Adjoint of the residual (FP64 precision only; LES_EUNSUPPORTED otherwise):
+/* Adjoint of the residual (FP64 precision and static or no SGS model only;
+ * LES_EUNSUPPORTED otherwise):
  *   Qbar = (dR/dQ)^T Rbar,
  * the vector-Jacobian product of R (section "Spatial Discretization") as a
  * function of the interior of Q, the ghost fill of section "Boundary
@@ -270,7 +274,8 @@ int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, do
  * kernels.  Qn as in les_rk5_step (ghosts overwritten, interior unchanged);
  * ghost entries of Qbar_np1 are ignored, those of Qbar_n are zero;
  * Qbar_n may alias Qbar_np1; inflow_bar as in les_residual_vjp (added to).
- * FP64 and LES_SCHEDULE_STAGE only (LES_EUNSUPPORTED otherwise).  Holds 25
+ * FP64, LES_SCHEDULE_STAGE and static or no SGS model only
+ * (LES_EUNSUPPORTED otherwise).  Holds 25
  * more padded variables after the first call.  Asynchronous on `stream`. */
 int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, double* Qbar_n,
                      double* inflow_bar, void* stream);

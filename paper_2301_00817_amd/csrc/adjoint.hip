@@ -18,7 +18,13 @@
 //      primitives are added -> cotangent of the padded state;
 //   4. transposes of the ghost fill in reverse order (zeta, eta, xi): ghost
 //      cotangents go to the points they were computed from, through the
-//      exact Jacobians of the boundary states (dual numbers).
+//      exact Jacobians of the boundary states (dual numbers);
+//   5. centerline through the nodes (axis_node): the transpose of the
+//      azimuthal mean that sets the axis row from row 1.
+// With axis_node the axis row has R = 0 and J^-1 = 0: its Rbar is ignored,
+// its eta point flux is the constant 0 and its point function is not
+// reversed (only its pressure sensors, which the axis face uses); the axis
+// face takes lambda_bar of row 1 and the fourth difference W2 - 4 W1 + 3 W0.
 #include "bc.hpp"
 #include "launch.hpp"
 #include "physics_vjp.hpp"
@@ -87,7 +93,8 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
   prim5(q, ph, pr);
   for (int c = 0; c < 5; ++c) SC[(long long)(S_PR + c) * g.vs + o] = pr[c];
   const double iV = trcp(M[9LL * g.vs + o]);
-  const bool inner = interior(g, i, j, k);
+  const bool axis_row = ph.axis_node && j == 0;        // R = 0, J^-1 = 0 there
+  const bool inner = interior(g, i, j, k) && !axis_row;
   for (int c = 0; c < 5; ++c)   // zero off the interior: R has no entries there
     SC[(long long)(S_RT + c) * g.vs + o] = inner ? Rb[(long long)c * g.vs + o] * iV : 0.0;
   if (!in_r1(g, i, j, k)) {
@@ -99,7 +106,7 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
     return;
   }
   const double a = tsqrt(pr[3]);
-  const double aiV = fabs(iV);
+  const double aiV = axis_row ? 0.0 : fabs(iV);        // axis row: no face uses its lambda_bar
   double lam[3];
   for (int d = 0; d < 3; ++d) {
     const double S0 = M[(long long)(3 * d) * g.vs + o], S1 = M[(long long)(3 * d + 1) * g.vs + o],
@@ -138,7 +145,9 @@ __device__ __forceinline__ void line_face(const double rt[5][5], const double lb
   for (int c = 0; c < 5; ++c) fc.Fb[c] = rt[f][c] - rt[f + 1][c];   // S_RT is zero off the interior
   fc.dis = !((L == -1 && ph.phys_face[d][0]) || (L == n - 1 && ph.phys_face[d][1]));
   const double nuL = nul[f], nuR = nul[f + 1];
-  fc.lf = 0.5 * (lbl[f] + lbl[f + 1]);
+  // the axis face (centerline through the nodes) takes lambda_bar of row 1
+  const bool axis = ph.axis_node && d == 1 && L == 0;
+  fc.lf = axis ? lbl[f + 1] : 0.5 * (lbl[f] + lbl[f + 1]);
   fc.Vf = 0.5 * (vl[f] + vl[f + 1]);
   fc.nu_left = nuL >= nuR;
   fc.e2 = ph.k2 * fmax(nuL, nuR);
@@ -167,6 +176,29 @@ __device__ __forceinline__ void face_self(const FaceCoef& f, const double* Wm, c
   }
   if (f.k4m > 0.0) e2_b -= e4_b;
   lbb += 0.5 * lf_b;
+  if (takes_nu) nub += ph.k2 * e2_b;
+}
+
+// The same at an inner point of the axis face, where
+// D = lf (e2 (W1 - W0) - e4 (W2 - 4 W1 + 3 W0)) and lf = lambda_bar(1):
+// W1 (the right point) takes lf (e2 + 4 e4), W0 lf (-e2 - 3 e4), and the
+// whole lf cotangent goes to the right point's lambda_bar.
+__device__ __forceinline__ void face_self_axis(const FaceCoef& f, const double* W0, const double* W1,
+                                               const double* W2, bool right, bool takes_nu,
+                                               const Phys<double>& ph, double wb[5], double& lbb,
+                                               double& nub) {
+  double lf_b = 0.0, e2_b = 0.0, e4_b = 0.0;
+  for (int c = 0; c < 5; ++c) {
+    const double Db = -f.Vf * f.Fb[c];
+    const double A = W1[c] - W0[c];
+    const double B = W2[c] - 4.0 * W1[c] + 3.0 * W0[c];
+    lf_b += Db * (f.e2 * A - f.e4 * B);
+    e2_b += Db * f.lf * A;
+    e4_b -= Db * f.lf * B;
+    wb[c] += (right ? f.lf * (f.e2 + 4.0 * f.e4) : -f.lf * (f.e2 + 3.0 * f.e4)) * Db;
+  }
+  if (f.k4m > 0.0) e2_b -= e4_b;
+  if (right) lbb += lf_b;
   if (takes_nu) nub += ph.k2 * e2_b;
 }
 
@@ -220,10 +252,13 @@ __global__ __launch_bounds__(256, LESJET_ADJ_MAIN_OCC) void k_adj_main(const dou
     line_face(rt, lbl, nul, vl, 3, d, s + 1, n, ph, fo[1]);
     line_face(rt, lbl, nul, vl, 1, d, s - 1, n, ph, fb);
     line_face(rt, lbl, nul, vl, 2, d, s, n, ph, fc);
+    // axis face (centerline through the nodes): face L = 0 along eta
+    const bool axd = ph.axis_node && d == 1;
     // faces L = s-2 and s+1: p is the outer point of their 4-point stencil
+    // (the axis face has no point -1 in its stencil)
     if (ha && fo[0].dis)
       for (int c = 0; c < 5; ++c) wb[c] += fo[0].lf * fo[0].e4 * fo[0].Vf * fo[0].Fb[c];
-    if (hd && fo[1].dis)
+    if (hd && fo[1].dis && !(axd && s + 1 == 0))
       for (int c = 0; c < 5; ++c) wb[c] -= fo[1].lf * fo[1].e4 * fo[1].Vf * fo[1].Fb[c];
     // faces L = s-1 (p is its right point) and L = s (p is its left point)
     for (int c = 0; c < 5; ++c)
@@ -238,8 +273,14 @@ __global__ __launch_bounds__(256, LESJET_ADJ_MAIN_OCC) void k_adj_main(const dou
         load5d(Q, g, om, W[m]);
         W[m][4] += SC[(long long)(S_PR + 4) * g.vs + om];
       }
-      if (db) face_self(fb, W[0], W[1], W[2], W[3], 1.0, !fb.nu_left, ph, wb, lbb[d], nub[d]);
-      if (dc) face_self(fc, W[1], W[2], W[3], W[4], -1.0, fc.nu_left, ph, wb, lbb[d], nub[d]);
+      if (db && axd && s - 1 == 0)
+        face_self_axis(fb, W[1], W[2], W[3], true, !fb.nu_left, ph, wb, lbb[d], nub[d]);
+      else if (db)
+        face_self(fb, W[0], W[1], W[2], W[3], 1.0, !fb.nu_left, ph, wb, lbb[d], nub[d]);
+      if (dc && axd && s == 0)
+        face_self_axis(fc, W[2], W[3], W[4], false, fc.nu_left, ph, wb, lbb[d], nub[d]);
+      else if (dc)
+        face_self(fc, W[1], W[2], W[3], W[4], -1.0, fc.nu_left, ph, wb, lbb[d], nub[d]);
     }
   }
 
@@ -267,7 +308,9 @@ __global__ __launch_bounds__(256, LESJET_ADJ_MAIN_OCC) void k_adj_main(const dou
     }
     in.V = M[9LL * g.vs + o];
     PointBar<double> bar = {};
-    point_quantities_vjp(in, ph, gb, lbb, bar);
+    // the axis row's point function is not reversed: its eta flux is the
+    // constant 0 and no other output of it is used (J^-1 = 0 there)
+    if (!(ph.axis_node && pos[1] == 0)) point_quantities_vjp(in, ph, gb, lbb, bar);
     for (int d = 0; d < 3; ++d) {
       double side, centre;
       sensor_vjp(pm[d], in.pr[4], pp[d], nub[d], side, centre);
@@ -361,6 +404,11 @@ __global__ __launch_bounds__(256) void k_adjT_eta(const double* __restrict__ Q, 
     // (nth is even, so the map is an involution of k)
     const int kk = (k + g.nth / 2) % g.nth;
     for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(i, m - 1, k), g.at(i, -m, kk));
+  } else if (lo_kind == BC_AXIS_NODE) {
+    // mirror through the axis node: the ghost (i, -m, k + nth/2) was copied
+    // from (i, m, k)
+    const int kk = (k + g.nth / 2) % g.nth;
+    for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(i, m, k), g.at(i, -m, kk));
   }
   if (hi_kind == BC_PERIODIC) {
     for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(i, m - 1, k), g.at(i, g.nr - 1 + m, k));
@@ -396,7 +444,7 @@ __global__ __launch_bounds__(256) void k_adjT_eta(const double* __restrict__ Q, 
 __global__ __launch_bounds__(64) void k_adjT_xi(const double* __restrict__ Q, const double* __restrict__ M,
                           double* __restrict__ Qb, Grid g, const double* __restrict__ inflow,
                           double* __restrict__ inflow_bar, double gamma, int lo_kind, int hi_kind,
-                          double p_exit) {
+                          double p_exit, int axis_node) {
   // one thread per (j, k) and face: the faces touch disjoint ghosts and
   // disjoint interior points
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -416,7 +464,10 @@ __global__ __launch_bounds__(64) void k_adjT_xi(const double* __restrict__ Q, co
       }
     }
   };
+  // boundary normals; on the axis row those of row 1 (S^xi vanishes there)
+  const int jn = axis_node && j == 0 ? 1 : j;
   auto normal = [&](int oe, double sgn, double n[3]) {
+    oe += (jn - j) * g.pitch;
     const double a = M[0LL * g.vs + oe], b = M[1LL * g.vs + oe], c = M[2LL * g.vs + oe];
     const double inv = sgn / sqrt(a * a + b * b + c * c);
     n[0] = a * inv; n[1] = b * inv; n[2] = c * inv;
@@ -458,6 +509,40 @@ __global__ __launch_bounds__(64) void k_adjT_xi(const double* __restrict__ Q, co
       Qb[(long long)jv * g.vs + oe] += acc;
     }
   }
+}
+
+// Transpose of the axis-row mean: Q(i, 0, k) = mean over k' of Q(i, 1, k'),
+// so the axis row's cotangent, summed over k, is spread evenly over row 1
+// and the axis row's own cotangent is zero.  One block per i, fixed-order
+// FP64 tree over k.
+constexpr int CLT_BS = 256;
+__global__ __launch_bounds__(CLT_BS) void k_adjT_centerline(double* __restrict__ Qb, Grid g) {
+  __shared__ double red[5][CLT_BS];
+  const int i = blockIdx.x;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < g.nth; k += CLT_BS) {
+    const int o = g.at(i, 0, k);
+    for (int c = 0; c < 5; ++c) acc[c] += Qb[(long long)c * g.vs + o];
+  }
+  for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = CLT_BS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 5; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < g.nth; k += CLT_BS) {
+    const int o0 = g.at(i, 0, k), o1 = g.at(i, 1, k);
+    for (int c = 0; c < 5; ++c) {
+      Qb[(long long)c * g.vs + o1] += red[c][0] / g.nth;
+      Qb[(long long)c * g.vs + o0] = 0.0;
+    }
+  }
+}
+
+hipError_t launch_centerline_transpose(double* Qb, const Grid& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjT_centerline, dim3(g.nx), dim3(CLT_BS), 0, s, Qb, g);
+  return hipGetLastError();
 }
 
 __global__ void k_scale(const double* __restrict__ x, double a, double* __restrict__ y,
@@ -510,7 +595,9 @@ hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
   hipLaunchKernelGGL(k_adjT_eta, dim3(blocks_for((long long)(g.nx + 2 * NG) * g.nth, 256)), dim3(256),
                      0, s, Q, M, Qb, g, gamma, bc[2], bc[3], ref);
   hipLaunchKernelGGL(k_adjT_xi, dim3(blocks_for(2LL * g.nr * g.nth, 64)), dim3(64), 0, s, Q, M, Qb,
-                     g, inflow, inflow_bar, gamma, bc[0], bc[1], p_exit);
+                     g, inflow, inflow_bar, gamma, bc[0], bc[1], p_exit, ph.axis_node);
+  if (bc[2] == BC_AXIS_NODE)
+    hipLaunchKernelGGL(k_adjT_centerline, dim3(g.nx), dim3(CLT_BS), 0, s, Qb, g);
   return hipGetLastError();
 }
 

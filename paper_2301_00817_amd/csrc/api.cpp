@@ -655,8 +655,6 @@ static int adjoint_ready(les_ctx* c) {
   if (r != LES_OK) return r;
   if (c->p.precision != LES_FP64)
     return fail(c, LES_EUNSUPPORTED, "the adjoint is available for the FP64 precision only");
-  if (c->p.bc[2] == LES_BC_AXIS_NODE)
-    return fail(c, LES_EUNSUPPORTED, "the adjoint does not cover the axis_node centerline");
   if (dynamic_model(c))
     return fail(c, LES_EUNSUPPORTED, "the adjoint does not cover the dynamic SGS model");
   return LES_OK;
@@ -710,6 +708,11 @@ int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, 
   // Qbar^n = b5 + b4 + ... + b0
   e = launch_scale(Qbar_np1, -al[4] * dt, B, v5, s);
   if (e == hipSuccess) e = launch_interior_copy(Qbar_np1, Qbar_n, c->g, s);
+  // centerline through the nodes: the returned axis row is the mean of the
+  // returned row 1, so its cotangent goes to row 1 first
+  if (e == hipSuccess && c->p.bc[2] == LES_BC_AXIS_NODE) e = launch_centerline_transpose(B, c->g, s);
+  if (e == hipSuccess && c->p.bc[2] == LES_BC_AXIS_NODE)
+    e = launch_centerline_transpose(Qbar_n, c->g, s);
   if (e != hipSuccess) return hip_fail(c, e, "rk5 adjoint kernels");
   for (int l = 5; l >= 1; --l) {
     if (l < 5) {

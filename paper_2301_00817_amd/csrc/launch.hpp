@@ -79,6 +79,10 @@ hipError_t launch_diagnostics(const double* Q, const TM* M, const Grid& g, const
 // entries zero); inflow_bar (5, nth, nr) accumulated when non-null.  Scratch
 // SC of VJP_SCRATCH_VARS padded variables; Q's ghosts must be filled.
 constexpr int VJP_SCRATCH_VARS = 36;
+// Transpose of the axis-row mean (centerline through the nodes) on a
+// cotangent field: the axis row's cotangent is spread over row 1, then zeroed.
+hipError_t launch_centerline_transpose(double* Qb, const Grid& g, hipStream_t s);
+
 hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
                                const Phys<double>& ph, const int bc[6], const double ref_prim[5],
                                double p_exit, const double* inflow, const double* Rb, double* SC,

@@ -260,7 +260,7 @@ int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed,
  *              entrance target (rho, u, v, w, p) is ADDED to it (only when
  *              xi- is an entrance).
  * Gather form without floating-point atomics: results are bitwise
- * reproducible.  Holds 36 scratch variables of the padded layout after the
+ * reproducible.  Holds 28 scratch variables of the padded layout after the
  * first call.  Asynchronous on `stream`. */
 int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, double* inflow_bar,
                      void* stream);

@@ -5,15 +5,16 @@
 // separately).  FP64, gather form: every output is accumulated by one
 // thread, with no floating-point atomics, so results are deterministic.
 //
-// Passes (36 scratch variables in the padded layout):
-//   1. primitives of every padded point; lambda_bar^d and nu^d of every
-//      point of [-1, n]^3; Rbar / J^-1 at the interior;
+// Passes (28 scratch variables in the padded layout):
+//   1. pressure of every padded point; 1 / J^-1, lambda_bar^d and nu^d of
+//      every point of [-1, n]^3 (zero at the other padded points);
 //   2. per padded point: cotangents of its G^d, lambda_bar^d, nu^d and W
 //      from the (up to) four faces per direction whose stencil contains it,
 //      then (points of [-1, n]^3) the reverse of the point function; the
 //      part of the state cotangent that depends on the point alone is
 //      finished here, the cotangents of its central differences and sensor
-//      neighbour pressures are stored;
+//      neighbour pressures are stored.  The xi and eta lines of a 16 x 16
+//      tile are staged in LDS;
 //   3. per padded point: the neighbours' contributions through its
 //      primitives are added -> cotangent of the padded state;
 //   4. transposes of the ghost fill in reverse order (zeta, eta, xi): ghost
@@ -61,52 +62,82 @@ __device__ __forceinline__ void wvec_at(const double* Q, const Grid& g, int o,
 
 // scratch layout (variables of the padded layout)
 enum {
-  S_PR = 0,    // (u, v, w, T, p) of every padded point
-  S_LB = 5,    // lambda_bar^d, points of [-1, n]^3
-  S_NU = 8,    // nu^d, points of [-1, n]^3
-  S_RT = 11,   // Rbar / J^-1 at interior points, 0 at the other padded points
-  S_PQ = 16,   // state cotangent of the point's own terms
-  S_DL = 21,   // cotangents of the central differences (d, u v w T), [-1, n]^3
-  S_NC = 33,   // cotangent of each sensor neighbour pressure (d), [-1, n]^3
-  S_N = 36
+  S_LB = 0,    // lambda_bar^d, points of [-1, n]^3
+  S_NU = 3,    // nu^d, points of [-1, n]^3
+  S_IV = 6,    // 1 / J^-1, points of [-1, n]^3
+  S_P = 7,     // pressure of every padded point
+  S_PQ = 8,    // state cotangent of the point's own terms
+  S_DL = 13,   // cotangents of the central differences (d, u v w T), [-1, n]^3
+  S_NC = 25,   // cotangent of each sensor neighbour pressure (d), [-1, n]^3
+  S_N = 28
 };
 static_assert(S_N == VJP_SCRATCH_VARS, "scratch size");
 
-// Pass 1, one thread per padded point: its primitives and Rbar / J^-1
-// (zero off the interior); for points of [-1, n]^3 also lambda_bar^d and
-// nu^d (the face dissipation coefficients, as in the point function).
+// Points of a padded plane by plane and XCD: workgroups are dealt to the
+// eight XCDs (each with its own L2) in turn; the block id is remapped so
+// that each XCD takes one eighth of every plane's blocks (256 points, or
+// one tile, each) and walks the planes in order, so the k-neighbour planes
+// a block reads were brought into the same L2 shortly before (with a plain
+// linear order a block's k-neighbours were fetched by blocks on other XCDs).
+constexpr int ADJ_NXCD = 8;
+struct PlaneMap {
+  int P;      // blocks per plane
+  int Pmax;   // of them per XCD
+};
+
+static PlaneMap plane_map(int blocks_per_plane) {
+  PlaneMap pm;
+  pm.P = blocks_per_plane;
+  pm.Pmax = (pm.P + ADJ_NXCD - 1) / ADJ_NXCD;
+  return pm;
+}
+
+static unsigned plane_map_grid(const PlaneMap& pm, const Grid& g) {
+  return (unsigned)(ADJ_NXCD * pm.Pmax * (g.nth + 2 * NG));
+}
+
+// Plane index (0 .. nth + 3) and block within the plane, or false for the
+// blocks that fill up the last XCD's share.
+__device__ __forceinline__ bool plane_block(const Grid& g, PlaneMap pm, int& kk, int& p) {
+  const int hw = blockIdx.x, x = hw % ADJ_NXCD, r = hw / ADJ_NXCD;
+  kk = r / pm.Pmax;
+  p = x * pm.Pmax + r % pm.Pmax;
+  return kk < g.nth + 2 * NG && p < pm.P;
+}
+
+// Pass 1, one thread per padded point: its pressure; for points of
+// [-1, n]^3 also 1 / J^-1, lambda_bar^d and nu^d (the face dissipation
+// coefficients, as in the point function), zero at the others.
 __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
                                                   const double* __restrict__ M, Grid g,
-                                                  Phys<double> ph, const double* __restrict__ Rb,
+                                                  Phys<double> ph, PlaneMap pm,
                                                   double* __restrict__ SC) {
-  const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG, NT = g.nth + 2 * NG;
-  const long long tot = (long long)NX * NR * NT;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= tot) return;
-  const int i = (int)(t % NX) - NG;
-  const int j = (int)((t / NX) % NR) - NG;
-  const int k = (int)(t / ((long long)NX * NR)) - NG;
+  int kk, pb;
+  if (!plane_block(g, pm, kk, pb)) return;
+  const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
+  const int q0 = pb * 256 + threadIdx.x;
+  if (q0 >= NX * NR) return;
+  const int i = q0 % NX - NG, j = q0 / NX - NG, k = kk - NG;
   const int o = g.at(i, j, k);
-  const int step[3] = {1, g.pitch, g.plane};
   double q[5], pr[5];
   load5d(Q, g, o, q);
   prim5(q, ph, pr);
-  for (int c = 0; c < 5; ++c) SC[(long long)(S_PR + c) * g.vs + o] = pr[c];
-  const double iV = trcp(M[9LL * g.vs + o]);
-  const bool axis_row = ph.axis_node && j == 0;        // R = 0, J^-1 = 0 there
-  const bool inner = interior(g, i, j, k) && !axis_row;
-  for (int c = 0; c < 5; ++c)   // zero off the interior: R has no entries there
-    SC[(long long)(S_RT + c) * g.vs + o] = inner ? Rb[(long long)c * g.vs + o] * iV : 0.0;
+  SC[(long long)S_P * g.vs + o] = pr[4];
   if (!in_r1(g, i, j, k)) {
     // no face uses these; written so that no pass reads unset memory
     for (int d = 0; d < 3; ++d) {
       SC[(long long)(S_LB + d) * g.vs + o] = 0.0;
       SC[(long long)(S_NU + d) * g.vs + o] = 0.0;
     }
+    SC[(long long)S_IV * g.vs + o] = 0.0;
     return;
   }
+  const int step[3] = {1, g.pitch, g.plane};
+  const bool axis_row = ph.axis_node && j == 0;        // J^-1 = 0 there
+  const double iV = trcp(M[9LL * g.vs + o]);
+  SC[(long long)S_IV * g.vs + o] = iV;
   const double a = tsqrt(pr[3]);
-  const double aiV = axis_row ? 0.0 : fabs(iV);        // axis row: no face uses its lambda_bar
+  const double aiV = axis_row ? 0.0 : fabs(iV);        // no face uses the axis row's
   double lam[3];
   for (int d = 0; d < 3; ++d) {
     const double S0 = M[(long long)(3 * d) * g.vs + o], S1 = M[(long long)(3 * d + 1) * g.vs + o],
@@ -116,8 +147,8 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
     double qm[5], qp[5];
     load5d(Q, g, o - step[d], qm);
     load5d(Q, g, o + step[d], qp);
-    const double pm = pressure(qm, ph), pp = pressure(qp, ph);
-    const double num = pp - 2.0 * pr[4] + pm, den = pp + 2.0 * pr[4] + pm;
+    const double pm_ = pressure(qm, ph), pp_ = pressure(qp, ph);
+    const double num = pp_ - 2.0 * pr[4] + pm_, den = pp_ + 2.0 * pr[4] + pm_;
     SC[(long long)(S_NU + d) * g.vs + o] = fabs(num) * trcp(den);
   }
   const double s01 = tsqrt(lam[0] * lam[1]), s02 = tsqrt(lam[0] * lam[2]),
@@ -142,7 +173,7 @@ struct FaceCoef {
 __device__ __forceinline__ void line_face(const double rt[5][5], const double lbl[5],
                                           const double nul[5], const double vl[5], int f, int d,
                                           int L, int n, const Phys<double>& ph, FaceCoef& fc) {
-  for (int c = 0; c < 5; ++c) fc.Fb[c] = rt[f][c] - rt[f + 1][c];   // S_RT is zero off the interior
+  for (int c = 0; c < 5; ++c) fc.Fb[c] = rt[f][c] - rt[f + 1][c];   // rt is zero off the interior
   fc.dis = !((L == -1 && ph.phys_face[d][0]) || (L == n - 1 && ph.phys_face[d][1]));
   const double nuL = nul[f], nuR = nul[f + 1];
   // the axis face (centerline through the nodes) takes lambda_bar of row 1
@@ -202,90 +233,91 @@ __device__ __forceinline__ void face_self_axis(const FaceCoef& f, const double* 
   if (takes_nu) nub += ph.k2 * e2_b;
 }
 
-// Pass 2, one thread per padded point p: the cotangents that the faces
-// whose stencils contain p send to its point quantities (G^d, lambda_bar^d,
-// nu^d) and to its W; then, for p in [-1, n]^3, the reverse of the point
-// function.  Writes the state cotangent of everything that depends on p
-// alone (S_PQ) and the cotangents of p's central differences and sensor
-// neighbour pressures (S_DL, S_NC), which pass 3 hands to the neighbours.
-#ifndef LESJET_ADJ_MAIN_OCC
-#define LESJET_ADJ_MAIN_OCC 1
-#endif
-__global__ __launch_bounds__(256, LESJET_ADJ_MAIN_OCC) void k_adj_main(const double* __restrict__ Q,
-                                                  const double* __restrict__ M, Grid g,
-                                                  Phys<double> ph, double* __restrict__ SC) {
-  const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG, NT = g.nth + 2 * NG;
-  const long long tot = (long long)NX * NR * NT;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= tot) return;
-  const int pos[3] = {(int)(t % NX) - NG, (int)((t / NX) % NR) - NG,
-                      (int)(t / ((long long)NX * NR)) - NG};
-  const int nn[3] = {g.nx, g.nr, g.nth};
-  const int step[3] = {1, g.pitch, g.plane};
-  const int o = g.at(pos[0], pos[1], pos[2]);
-  const bool r1 = in_r1(g, pos[0], pos[1], pos[2]);
-  double gb[3][5], lbb[3] = {0, 0, 0}, nub[3] = {0, 0, 0}, wb[5] = {0, 0, 0, 0, 0};
-  for (int d = 0; d < 3; ++d)
-    for (int c = 0; c < 5; ++c) gb[d][c] = 0.0;
-
-  for (int d = 0; d < 3; ++d) {
-    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
-    if (pos[d1] < 0 || pos[d1] >= nn[d1] || pos[d2] < 0 || pos[d2] >= nn[d2]) continue;
-    const int s = pos[d], sd = step[d], n = nn[d];
-    // the line p-2 .. p+2 along d (points outside the padded box, reached
-    // only when p is a ghost, are clamped to its edge; no existing face uses
-    // them); face L = s-2+f joins line points f and f+1
-    double rt[5][5], lbl[5], nul[5], vl[5];
-    for (int m = 0; m < 5; ++m) {
-      const int pt = min(max(s + m - 2, -NG), n - 1 + NG);
-      const int om = o + (pt - s) * sd;
-      for (int c = 0; c < 5; ++c) rt[m][c] = SC[(long long)(S_RT + c) * g.vs + om];
-      lbl[m] = SC[(long long)(S_LB + d) * g.vs + om];
-      nul[m] = SC[(long long)(S_NU + d) * g.vs + om];
-      vl[m] = M[9LL * g.vs + om];
-    }
-    FaceCoef fo[2], fb, fc;
-    // faces exist for L in [-1, n-1]
-    const bool ha = s - 2 >= -1, hd = s + 1 <= n - 1;
-    const bool hb = s - 1 >= -1 && s - 1 <= n - 1, hc = s >= -1 && s <= n - 1;
-    line_face(rt, lbl, nul, vl, 0, d, s - 2, n, ph, fo[0]);
-    line_face(rt, lbl, nul, vl, 3, d, s + 1, n, ph, fo[1]);
-    line_face(rt, lbl, nul, vl, 1, d, s - 1, n, ph, fb);
-    line_face(rt, lbl, nul, vl, 2, d, s, n, ph, fc);
-    // axis face (centerline through the nodes): face L = 0 along eta
-    const bool axd = ph.axis_node && d == 1;
-    // faces L = s-2 and s+1: p is the outer point of their 4-point stencil
-    // (the axis face has no point -1 in its stencil)
-    if (ha && fo[0].dis)
-      for (int c = 0; c < 5; ++c) wb[c] += fo[0].lf * fo[0].e4 * fo[0].Vf * fo[0].Fb[c];
-    if (hd && fo[1].dis && !(axd && s + 1 == 0))
-      for (int c = 0; c < 5; ++c) wb[c] -= fo[1].lf * fo[1].e4 * fo[1].Vf * fo[1].Fb[c];
-    // faces L = s-1 (p is its right point) and L = s (p is its left point)
-    for (int c = 0; c < 5; ++c)
-      gb[d][c] = 0.5 * ((hb ? fb.Fb[c] : 0.0) + (hc ? fc.Fb[c] : 0.0));
-    const bool db = hb && fb.dis, dc = hc && fc.dis;
-    if (db || dc) {
-      // W on the line p-2 .. p+2, clamped like the other line values
-      double W[5][5];
-      for (int m = 0; m < 5; ++m) {
-        const int pt = min(max(s + m - 2, -NG), n - 1 + NG);
-        const int om = o + (pt - s) * sd;
-        load5d(Q, g, om, W[m]);
-        W[m][4] += SC[(long long)(S_PR + 4) * g.vs + om];
-      }
-      if (db && axd && s - 1 == 0)
-        face_self_axis(fb, W[1], W[2], W[3], true, !fb.nu_left, ph, wb, lbb[d], nub[d]);
-      else if (db)
-        face_self(fb, W[0], W[1], W[2], W[3], 1.0, !fb.nu_left, ph, wb, lbb[d], nub[d]);
-      if (dc && axd && s == 0)
-        face_self_axis(fc, W[2], W[3], W[4], false, fc.nu_left, ph, wb, lbb[d], nub[d]);
-      else if (dc)
-        face_self(fc, W[1], W[2], W[3], W[4], -1.0, fc.nu_left, ph, wb, lbb[d], nub[d]);
-    }
+// Line p-2 .. p+2 along zeta read from global memory (points outside the
+// padded box, reached only when p is a ghost, are clamped to its edge; no
+// existing face uses them).  Rbar / J^-1 is zero off the interior (and on
+// the axis row of a centerline-through-the-nodes mesh, where R = 0);
+// W = (rho, rho u, rho v, rho w, E + p).
+struct ZetaLine {
+  const double* Q;
+  const double* M;
+  const double* Rb;
+  const double* SC;
+  int vs, o, plane, s, n;
+  bool row_inner;     // (i, j) of p is interior and not on the axis row
+  __device__ __forceinline__ int pt(int m) const { return min(max(s + m - 2, -NG), n - 1 + NG); }
+  __device__ __forceinline__ void coef(int m, double rt[5], double& lb, double& nu, double& v) const {
+    const int k = pt(m), om = o + (k - s) * plane;
+    v = M[9LL * vs + om];
+    const double iV = SC[(long long)S_IV * vs + om];
+    const bool inner = row_inner && k >= 0 && k < n;
+    for (int c = 0; c < 5; ++c) rt[c] = inner ? Rb[(long long)c * vs + om] * iV : 0.0;
+    lb = SC[(long long)(S_LB + 2) * vs + om];
+    nu = SC[(long long)(S_NU + 2) * vs + om];
   }
+  __device__ __forceinline__ void w(int m, double W[5]) const {
+    const int om = o + (pt(m) - s) * plane;
+    for (int c = 0; c < 5; ++c) W[c] = Q[(long long)c * vs + om];
+    W[4] += SC[(long long)S_P * vs + om];
+  }
+};
 
+// Contributions of the four faces along d whose stencil holds p (line
+// position s of n interior points): p's W (wb), its G^d (gbd), lambda_bar^d
+// (lbb) and nu^d (nub).
+template <class Line>
+__device__ __forceinline__ void dir_part(const Line& ln, int s, int d, int n, const Phys<double>& ph,
+                                         double wb[5], double gbd[5], double& lbb, double& nub) {
+  // face L = s-2+f joins line points f and f+1
+  double rt[5][5], lbl[5], nul[5], vl[5];
+  for (int m = 0; m < 5; ++m) ln.coef(m, rt[m], lbl[m], nul[m], vl[m]);
+  FaceCoef fo[2], fb, fc;
+  // faces exist for L in [-1, n-1]
+  const bool ha = s - 2 >= -1, hd = s + 1 <= n - 1;
+  const bool hb = s - 1 >= -1 && s - 1 <= n - 1, hc = s >= -1 && s <= n - 1;
+  line_face(rt, lbl, nul, vl, 0, d, s - 2, n, ph, fo[0]);
+  line_face(rt, lbl, nul, vl, 3, d, s + 1, n, ph, fo[1]);
+  line_face(rt, lbl, nul, vl, 1, d, s - 1, n, ph, fb);
+  line_face(rt, lbl, nul, vl, 2, d, s, n, ph, fc);
+  // axis face (centerline through the nodes): face L = 0 along eta
+  const bool axd = ph.axis_node && d == 1;
+  // faces L = s-2 and s+1: p is the outer point of their 4-point stencil
+  // (the axis face has no point -1 in its stencil)
+  if (ha && fo[0].dis)
+    for (int c = 0; c < 5; ++c) wb[c] += fo[0].lf * fo[0].e4 * fo[0].Vf * fo[0].Fb[c];
+  if (hd && fo[1].dis && !(axd && s + 1 == 0))
+    for (int c = 0; c < 5; ++c) wb[c] -= fo[1].lf * fo[1].e4 * fo[1].Vf * fo[1].Fb[c];
+  // faces L = s-1 (p is its right point) and L = s (p is its left point)
+  for (int c = 0; c < 5; ++c) gbd[c] = 0.5 * ((hb ? fb.Fb[c] : 0.0) + (hc ? fc.Fb[c] : 0.0));
+  const bool db = hb && fb.dis, dc = hc && fc.dis;
+  if (db || dc) {
+    double W[5][5];
+    for (int m = 0; m < 5; ++m) ln.w(m, W[m]);
+    if (db && axd && s - 1 == 0)
+      face_self_axis(fb, W[1], W[2], W[3], true, !fb.nu_left, ph, wb, lbb, nub);
+    else if (db)
+      face_self(fb, W[0], W[1], W[2], W[3], 1.0, !fb.nu_left, ph, wb, lbb, nub);
+    if (dc && axd && s == 0)
+      face_self_axis(fc, W[2], W[3], W[4], false, fc.nu_left, ph, wb, lbb, nub);
+    else if (dc)
+      face_self(fc, W[1], W[2], W[3], W[4], -1.0, fc.nu_left, ph, wb, lbb, nub);
+  }
+}
+
+// Second half of pass 2 at p, once the face contributions are summed: for
+// p in [-1, n]^3 the reverse of the point function (skipped on the axis row
+// of a centerline-through-the-nodes mesh, whose eta flux is the constant 0
+// and whose other outputs are unused since J^-1 = 0 there), the sensor
+// reverse and the writes of S_NC, S_DL; for every p the reverse of the
+// primitives -> S_PQ.
+template <class Prim>
+__device__ __forceinline__ void point_part(const double* __restrict__ M, double* __restrict__ SC,
+                                           const Grid& g, int o, bool r1,
+                                           bool axis_row, const Phys<double>& ph, const Prim& pv,
+                                           const double gb[3][5], double lbb[3], const double nub[3],
+                                           const double wb[5]) {
   double q[5];
-  load5d(Q, g, o, q);
+  pv.state(q);
   double qb[5], prb[5] = {0, 0, 0, 0, 0};
   for (int c = 0; c < 5; ++c) qb[c] = wb[c];
   prb[4] = wb[4];                                  // W5 = E + p
@@ -293,24 +325,22 @@ __global__ __launch_bounds__(256, LESJET_ADJ_MAIN_OCC) void k_adj_main(const dou
     PointIn<double> in;
     for (int c = 0; c < 5; ++c) {
       in.q[c] = q[c];
-      in.pr[c] = SC[(long long)(S_PR + c) * g.vs + o];
+      in.pr[c] = pv.own(c);
     }
     double pm[3], pp[3];
     for (int d = 0; d < 3; ++d) {
       double m[5], pl[5];
-      load5d(SC + (long long)S_PR * g.vs, g, o - step[d], m);
-      load5d(SC + (long long)S_PR * g.vs, g, o + step[d], pl);
+      pv.nb(d, -1, m);
+      pv.nb(d, 1, pl);
       for (int f = 0; f < 4; ++f) in.dl[d][f] = 0.5 * (pl[f] - m[f]);
       in.nu[d] = 0.0;                        // not used by the reverse
       pm[d] = m[4];
       pp[d] = pl[4];
       for (int c = 0; c < 3; ++c) in.S[d][c] = M[(long long)(3 * d + c) * g.vs + o];
     }
-    in.V = M[9LL * g.vs + o];
+    in.V = pv.vol();
     PointBar<double> bar = {};
-    // the axis row's point function is not reversed: its eta flux is the
-    // constant 0 and no other output of it is used (J^-1 = 0 there)
-    if (!(ph.axis_node && pos[1] == 0)) point_quantities_vjp(in, ph, gb, lbb, bar);
+    if (!axis_row) point_quantities_vjp(in, ph, gb, lbb, bar);
     for (int d = 0; d < 3; ++d) {
       double side, centre;
       sensor_vjp(pm[d], in.pr[4], pp[d], nub[d], side, centre);
@@ -327,16 +357,137 @@ __global__ __launch_bounds__(256, LESJET_ADJ_MAIN_OCC) void k_adj_main(const dou
   for (int c = 0; c < 5; ++c) SC[(long long)(S_PQ + c) * g.vs + o] = qb[c];
 }
 
+// Pass 2, one thread per padded point p: the cotangents that the faces
+// whose stencils contain p send to its point quantities (G^d, lambda_bar^d,
+// nu^d) and to its W; then, for p in [-1, n]^3, the reverse of the point
+// function.  Writes the state cotangent of everything that depends on p
+// alone (S_PQ) and the cotangents of p's central differences and sensor
+// neighbour pressures (S_DL, S_NC), which pass 3 hands to the neighbours.
+//
+// One block per 16 x 16 tile of a padded plane.  The block stages once, in
+// LDS, what the xi and eta lines of its points read (the tile and two points
+// on each side, clamped to the padded box): Rbar / J^-1, lambda_bar and nu
+// along xi and eta, J^-1, the state and the primitives.  The zeta lines and
+// the metrics come from global memory.
+constexpr int AT_X = 16, AT_Y = 16, AT_HX = AT_X + 4, AT_HY = AT_Y + 4, AT_HP = AT_HX * AT_HY;
+enum { L_RT = 0, L_LB = 5, L_NU = 7, L_V = 9, L_Q = 10, L_PR = 15, L_N = 20 };
+
+struct LdsLine {
+  const double* sh;   // [L_N][AT_HP]
+  int slot;           // slot of line point 0
+  int stride;         // 1 along xi, AT_HX along eta
+  int d;
+  __device__ __forceinline__ void coef(int m, double rt[5], double& lb, double& nu, double& v) const {
+    const int e = slot + m * stride;
+    for (int c = 0; c < 5; ++c) rt[c] = sh[(L_RT + c) * AT_HP + e];
+    lb = sh[(L_LB + d) * AT_HP + e];
+    nu = sh[(L_NU + d) * AT_HP + e];
+    v = sh[L_V * AT_HP + e];
+  }
+  __device__ __forceinline__ void w(int m, double W[5]) const {
+    const int e = slot + m * stride;
+    for (int c = 0; c < 5; ++c) W[c] = sh[(L_Q + c) * AT_HP + e];
+    W[4] += sh[(L_PR + 4) * AT_HP + e];
+  }
+};
+
+// State and primitives of p, primitives of its neighbours p -+ 1 along d
+// (LDS in the plane, global state along zeta), J^-1 of p.
+struct LdsPoint {
+  const double* sh;
+  const double* Q;
+  const Phys<double>* ph;
+  int slot, vs, o, plane;
+  __device__ __forceinline__ void state(double q[5]) const {
+    for (int c = 0; c < 5; ++c) q[c] = sh[(L_Q + c) * AT_HP + slot];
+  }
+  __device__ __forceinline__ double own(int c) const { return sh[(L_PR + c) * AT_HP + slot]; }
+  __device__ __forceinline__ void nb(int d, int sg, double pr[5]) const {
+    if (d < 2) {
+      const int e = slot + sg * (d == 0 ? 1 : AT_HX);
+      for (int c = 0; c < 5; ++c) pr[c] = sh[(L_PR + c) * AT_HP + e];
+    } else {
+      double qn[5];
+      for (int c = 0; c < 5; ++c) qn[c] = Q[(long long)c * vs + o + sg * plane];
+      prim5(qn, *ph, pr);
+    }
+  }
+  __device__ __forceinline__ double vol() const { return sh[L_V * AT_HP + slot]; }
+};
+
+__global__ __launch_bounds__(256) void k_adj_main(const double* __restrict__ Q,
+                                                  const double* __restrict__ M, Grid g,
+                                                  Phys<double> ph, PlaneMap pm, int tiles_x,
+                                                  const double* __restrict__ Rb,
+                                                  double* __restrict__ SC) {
+  __shared__ double sh[L_N * AT_HP];
+  int kk, pb;
+  if (!plane_block(g, pm, kk, pb)) return;   // uniform over the block
+  const int i0 = (pb % tiles_x) * AT_X - NG, j0 = (pb / tiles_x) * AT_Y - NG, k = kk - NG;
+  for (int e = threadIdx.x; e < AT_HP; e += 256) {
+    const int i = min(max(i0 + e % AT_HX - 2, -NG), g.nx - 1 + NG);
+    const int j = min(max(j0 + e / AT_HX - 2, -NG), g.nr - 1 + NG);
+    const int oe = g.at(i, j, k);
+    double q[5], pr[5];
+    load5d(Q, g, oe, q);
+    prim5(q, ph, pr);
+    const double V = M[9LL * g.vs + oe], iV = SC[(long long)S_IV * g.vs + oe];
+    // R has no entries off the interior nor on a centerline row
+    const bool inner = interior(g, i, j, k) && !(ph.axis_node && j == 0);
+    for (int c = 0; c < 5; ++c) {
+      sh[(L_RT + c) * AT_HP + e] = inner ? Rb[(long long)c * g.vs + oe] * iV : 0.0;
+      sh[(L_Q + c) * AT_HP + e] = q[c];
+      sh[(L_PR + c) * AT_HP + e] = pr[c];
+    }
+    for (int d = 0; d < 2; ++d) {
+      sh[(L_LB + d) * AT_HP + e] = SC[(long long)(S_LB + d) * g.vs + oe];
+      sh[(L_NU + d) * AT_HP + e] = SC[(long long)(S_NU + d) * g.vs + oe];
+    }
+    sh[L_V * AT_HP + e] = V;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % AT_X, ty = threadIdx.x / AT_X;
+  const int pos[3] = {i0 + tx, j0 + ty, k};
+  if (pos[0] >= g.nx + NG || pos[1] >= g.nr + NG) return;
+  const int slot = (ty + 2) * AT_HX + tx + 2;
+  const int nn[3] = {g.nx, g.nr, g.nth};
+  const int o = g.at(pos[0], pos[1], pos[2]);
+  const bool r1 = in_r1(g, pos[0], pos[1], pos[2]);
+  double gb[3][5], lbb[3] = {0, 0, 0}, nub[3] = {0, 0, 0}, wb[5] = {0, 0, 0, 0, 0};
+  for (int d = 0; d < 3; ++d)
+    for (int c = 0; c < 5; ++c) gb[d][c] = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    // faces along d exist only where p is interior in the other directions
+    const int d1 = d == 2 ? 0 : d + 1, d2 = d == 0 ? 2 : d - 1;
+    if (pos[d1] < 0 || pos[d1] >= nn[d1] || pos[d2] < 0 || pos[d2] >= nn[d2]) continue;
+    if (d < 2) {
+      const int stride = d == 0 ? 1 : AT_HX;
+      const LdsLine ln = {sh, slot - 2 * stride, stride, d};
+      dir_part(ln, pos[d], d, nn[d], ph, wb, gb[d], lbb[d], nub[d]);
+    } else {
+      const ZetaLine ln = {Q, M, Rb, SC, g.vs, o, g.plane, pos[2], g.nth,
+                           !(ph.axis_node && pos[1] == 0)};
+      dir_part(ln, pos[2], 2, g.nth, ph, wb, gb[2], lbb[2], nub[2]);
+    }
+  }
+  const LdsPoint pv = {sh, Q, &ph, slot, g.vs, o, g.plane};
+  point_part(M, SC, g, o, r1, ph.axis_node && pos[1] == 0, ph, pv, gb, lbb, nub, wb);
+}
+
 // Pass 3: cotangent of the padded state = own part + the neighbours'
 // central-difference and sensor contributions through this point's
 // primitives.  One thread per element of a variable, so the pitch padding
 // beyond the padded box is written (zero) too.
 __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ Q, Grid g,
                                                     Phys<double> ph,
-                                                    const double* __restrict__ SC,
+                                                    PlaneMap pm, const double* __restrict__ SC,
                                                     double* __restrict__ Qb) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= g.vs) return;
+  // 256-element blocks of a padded plane (pitch included) by plane and XCD
+  int kk, p;
+  if (!plane_block(g, pm, kk, p)) return;
+  const int q = p * 256 + threadIdx.x;
+  if (q >= g.plane) return;
+  const int o = kk * g.plane + q;
   const int pos[3] = {o % g.pitch - NG, (o % g.plane) / g.pitch - NG, o / g.plane - NG};
   if (pos[0] >= g.nx + NG) {
     for (int c = 0; c < 5; ++c) Qb[(long long)c * g.vs + o] = 0.0;
@@ -584,10 +735,15 @@ hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
                                const Phys<double>& ph, const int bc[6], const double ref_prim[5],
                                double p_exit, const double* inflow, const double* Rb, double* SC,
                                double* Qb, double* inflow_bar, hipStream_t s) {
-  const long long npad = (long long)(g.nx + 2 * NG) * (g.nr + 2 * NG) * (g.nth + 2 * NG);
-  hipLaunchKernelGGL(k_adj_prep, dim3(blocks_for(npad, 256)), dim3(256), 0, s, Q, M, g, ph, Rb, SC);
-  hipLaunchKernelGGL(k_adj_main, dim3(blocks_for(npad, 256)), dim3(256), 0, s, Q, M, g, ph, SC);
-  hipLaunchKernelGGL(k_adj_gather, dim3(blocks_for(g.vs, 256)), dim3(256), 0, s, Q, g, ph, SC, Qb);
+  const PlaneMap ppm = plane_map(((g.nx + 2 * NG) * (g.nr + 2 * NG) + 255) / 256);
+  hipLaunchKernelGGL(k_adj_prep, dim3(plane_map_grid(ppm, g)), dim3(256), 0, s, Q, M, g, ph, ppm, SC);
+  const int tiles_x = (g.nx + 2 * NG + AT_X - 1) / AT_X;
+  const PlaneMap tpm = plane_map(tiles_x * ((g.nr + 2 * NG + AT_Y - 1) / AT_Y));
+  hipLaunchKernelGGL(k_adj_main, dim3(plane_map_grid(tpm, g)), dim3(256), 0, s, Q, M, g, ph, tpm,
+                     tiles_x, Rb, SC);
+  const PlaneMap gpm = plane_map((g.plane + 255) / 256);
+  hipLaunchKernelGGL(k_adj_gather, dim3(plane_map_grid(gpm, g)), dim3(256), 0, s, Q, g, ph, gpm, SC,
+                     Qb);
   const double gamma = ph.gamma;
   hipLaunchKernelGGL(k_adjT_zeta, dim3(blocks_for((long long)(g.nx + 2 * NG) * (g.nr + 2 * NG), 256)),
                      dim3(256), 0, s, Qb, g);

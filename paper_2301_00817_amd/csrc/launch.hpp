@@ -78,7 +78,7 @@ hipError_t launch_diagnostics(const double* Q, const TM* M, const Grid& g, const
 // Residual adjoint (FP64): Qb = (dR/dQ)^T Rb on the padded layout (ghost
 // entries zero); inflow_bar (5, nth, nr) accumulated when non-null.  Scratch
 // SC of VJP_SCRATCH_VARS padded variables; Q's ghosts must be filled.
-constexpr int VJP_SCRATCH_VARS = 36;
+constexpr int VJP_SCRATCH_VARS = 28;
 // Transpose of the axis-row mean (centerline through the nodes) on a
 // cotangent field: the axis row's cotangent is spread over row 1, then zeroed.
 hipError_t launch_centerline_transpose(double* Qb, const Grid& g, hipStream_t s);

@@ -7,8 +7,9 @@ test_oracle_adjoint.py).  Cases:
     dR/dQ and of dR/d(inflow data) from les_residual_vjp with unit
     cotangents, against the complex-step Jacobian, per row <= 1e-12;
   * directional checks <Rbar, J v> = <Qbar, v> on a periodic box and a
-    24x12x16 jet with the Smagorinsky and with the Vreman model, and on the
-    full 160x100x128 jet mesh with a seeded Gaussian cotangent;
+    24x12x16 jet with the Smagorinsky and with the Vreman model, on thin
+    meshes (tile edges of the main pass), and on the full 160x100x128 jet
+    mesh with a seeded Gaussian cotangent;
   * RK5-step adjoint against complex-step derivatives of the oracle's RK5
     step (fixed dt), including the entrance-data cotangent and in-place use;
   * central differences of the GPU's own forward residual (dot-product
@@ -136,6 +137,41 @@ def test_vjp_directional(case):
         rhs = float(np.sum(to_np(ib) * vin))
         print(case, "inflow", lhs, rhs, _rel(rhs, lhs))
         assert _rel(rhs, lhs) <= 1e-11
+
+
+THIN = {
+    # the main pass works on 16 x 16 tiles of the padded plane (nx + 4 by
+    # nr + 4): many tiles along one direction and a part of one along the
+    # other, exactly two tiles along xi with one row in a second tile along
+    # eta, and the smallest box (one partial tile)
+    "jet300x5x6": lambda: _jet(300, 5, 6, seed=21),
+    "jet5x40x6": lambda: _jet(5, 40, 6, seed=22),
+    "jet28x13x8": lambda: _jet(28, 13, 8, seed=23),
+    "box5": lambda: problems.box_problem(5, seed=24, noise=1e-3),
+}
+
+
+@pytest.mark.parametrize("case", list(THIN))
+def test_vjp_directional_thin_meshes(case):
+    pb = THIN[case]()
+    announce("vjp thin mesh", case)
+    geo = _geo(pb)
+    Q = pb["Q"].numpy()
+    Rbar = problems.seeded_field(Q.shape, 3, flow.FIELD_COTANGENT).numpy()
+    s = make_solver(pb)
+    Qp = s.pad(pb["Q"].cuda())
+    Rb = s.pad(torch.from_numpy(Rbar).cuda(), fill=0.0)
+    ib = s.new_inflow_bar() if pb["inflow"] is not None else None
+    Qb = to_np(s.interior(s.residual_vjp(Qp, Rb, inflow_bar=ib)))
+    v = problems.seeded_field(Q.shape, 11, flow.FIELD_DIRECTION).numpy()
+    vin = None
+    if ib is not None:
+        vin = problems.seeded_field(tuple(pb["inflow"].shape), 13, flow.FIELD_DIRECTION_IN).numpy()
+    lhs = float(np.sum(Rbar * _oracle_jv(pb, geo, v, vin)))
+    rhs = float(np.sum(Qb * v)) + (float(np.sum(to_np(ib) * vin)) if ib is not None else 0.0)
+    print(case, lhs, rhs, _rel(rhs, lhs))
+    assert _rel(rhs, lhs) <= 1e-11
+    s.close()
 
 
 def test_vjp_full_jet_mesh():

@@ -52,12 +52,6 @@ __device__ __forceinline__ double pressure(const double q[5], const Phys<double>
   return ph.gm1 * (q[4] - 0.5 * q[0] * (u * u + v * v + w * w));
 }
 
-__device__ __forceinline__ void wvec_at(const double* Q, const Grid& g, int o,
-                                        const Phys<double>& ph, double W[5]) {
-  load5d(Q, g, o, W);
-  W[4] += pressure(W, ph);
-}
-
 }  // namespace
 
 // scratch layout (variables of the padded layout)
@@ -133,11 +127,13 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
     return;
   }
   const int step[3] = {1, g.pitch, g.plane};
-  const bool axis_row = ph.axis_node && j == 0;        // J^-1 = 0 there
-  const double iV = trcp(M[9LL * g.vs + o]);
+  // J^-1 = 0 on the axis row of a centerline-through-the-nodes mesh: no face
+  // uses its lambda_bar and its Rbar is ignored, so 0 is stored there
+  const bool axis_row = ph.axis_node && j == 0;
+  const double iV = axis_row ? 0.0 : trcp(M[9LL * g.vs + o]);
   SC[(long long)S_IV * g.vs + o] = iV;
   const double a = tsqrt(pr[3]);
-  const double aiV = axis_row ? 0.0 : fabs(iV);        // no face uses the axis row's
+  const double aiV = fabs(iV);
   double lam[3];
   for (int d = 0; d < 3; ++d) {
     const double S0 = M[(long long)(3 * d) * g.vs + o], S1 = M[(long long)(3 * d + 1) * g.vs + o],
@@ -147,8 +143,8 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
     double qm[5], qp[5];
     load5d(Q, g, o - step[d], qm);
     load5d(Q, g, o + step[d], qp);
-    const double pm_ = pressure(qm, ph), pp_ = pressure(qp, ph);
-    const double num = pp_ - 2.0 * pr[4] + pm_, den = pp_ + 2.0 * pr[4] + pm_;
+    const double pl = pressure(qm, ph), pu = pressure(qp, ph);
+    const double num = pu - 2.0 * pr[4] + pl, den = pu + 2.0 * pr[4] + pl;
     SC[(long long)(S_NU + d) * g.vs + o] = fabs(num) * trcp(den);
   }
   const double s01 = tsqrt(lam[0] * lam[1]), s02 = tsqrt(lam[0] * lam[2]),

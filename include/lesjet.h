@@ -125,7 +125,7 @@ enum les_bc {
  *                (1/4, 1/2, 1/4) test filter and Delta_hat = 2 Delta before
  *                every residual (LES_SCHEDULE_STEP: once per step); C_I, C_ds
  *                below zero are taken as zero, Pr_sgs falls back to the static
- *                value when not a positive number.  Cs is not used.  Holds 15
+ *                value when not a positive number.  Cs is not used.  Holds 29
  *                FP64 scratch variables of the padded layout.  Not available
  *                with LES_BC_AXIS_NODE (les_validate: LES_EUNSUPPORTED). */
 enum les_sgs {

@@ -7,30 +7,46 @@
 // point).  Computed in FP64 from the state of the storage type; the sums are
 // fixed-order trees (reproducible).
 //
-//   k_dyn_fields  points of [-1, n]^3: rho |S| S_ij, rho |S|^2, rho |S| dT/dx_j
-//                 (central differences, chain rule) and the filtered rho,
-//                 rho u_i, rho T (27 points of the padded box);
-//   k_dyn_sums    interior points: the remaining filtered quantities, the
-//                 strain of u_hat = hat(rho u)/hat(rho) and the gradient of
-//                 T_hat = hat(rho T)/hat(rho); per block, the J^-1-weighted
-//                 sums of the seven numerator and denominator terms;
+// The separable filter is applied one direction at a time:
+//   k_dyn_plane   per 16 x 16 tile of a plane: the raw fields of the tile
+//                 and a one-point ring (rho |S| S_ij, rho |S|^2,
+//                 rho |S| dT/dx_j from central differences and the chain
+//                 rule; rho u_i u_j, rho u_i T; rho, rho u_i, rho T) formed
+//                 once per point into LDS, filtered along i and j there and
+//                 stored;
+//   k_dyn_hat     points of [-1, n]^3: the filter along k of rho, rho u_i,
+//                 rho T -> hat(rho), hat(rho u_i), hat(rho T);
+//   k_dyn_sums    interior points: the filter along k of the other fields,
+//                 the strain of u_hat = hat(rho u)/hat(rho) and the gradient
+//                 of T_hat = hat(rho T)/hat(rho); per block, the
+//                 J^-1-weighted sums of the seven numerator and denominator
+//                 terms;
 //   k_dyn_final   one block: the sums, the coefficients, clipping.
 #include "launch.hpp"
+#include "physics.hpp"
 
 namespace lesjet {
 
+// Fields filtered along i and j (index within the 24 filtered fields and
+// scratch variable), then the fully filtered state.
 enum {
-  DY_FS = 0,     // rho |S| S_ij, ij = 00 11 22 01 02 12
+  DY_FS = 0,     // rho |S| S_ij, ij = 00 11 22 01 02 12    (i, j in [0, n), k in [-1, n])
   DY_FS2 = 6,    // rho |S|^2
   DY_FT = 7,     // rho |S| dT/dx_j
-  DY_HR = 10,    // hat(rho)
-  DY_HRU = 11,   // hat(rho u_i)
-  DY_HRT = 14,   // hat(rho T)
-  DY_N = 15
+  DY_PUU = 10,   // rho u_i u_j, ij = 00 11 22 01 02 12
+  DY_PUT = 16,   // rho u_i T
+  DY_NG = 19,    // fields used at interior points only
+  DY_R = 19,     // rho, rho u_i, rho T                      (i, j in [-1, n], every plane)
+  DY_NF = 24,
+  DY_HR = 24,    // hat(rho)                                 ([-1, n]^3)
+  DY_HRU = 25,   // hat(rho u_i)
+  DY_HRT = 28,   // hat(rho T)
+  DY_N = 29
 };
 static_assert(DY_N == DYN_SCRATCH_VARS, "dynamic-model scratch size");
 
 constexpr int DY_BS = 256;
+constexpr int DY_NXCD = 8;   // XCDs of the device (workgroups are dealt to them in turn)
 constexpr int DY_NSUM = 7;   // N_I, D_I, A, B, D_d, N_P, D_P
 static_assert(DY_NSUM + 6 + 3 <= DYN_COEF_DOUBLES, "coefficient buffer size");
 
@@ -47,7 +63,7 @@ __device__ __forceinline__ PrimD prim_at(const T* __restrict__ Q, const Grid& g,
   const double q0 = (double)Q[o], q1 = (double)Q[(long long)g.vs + o],
                q2 = (double)Q[2LL * g.vs + o], q3 = (double)Q[3LL * g.vs + o],
                q4 = (double)Q[4LL * g.vs + o];
-  const double ir = 1.0 / q0;          // one division per point
+  const double ir = trcp(q0);          // one reciprocal per point
   s.rho = q0;
   s.u = q1 * ir;
   s.v = q2 * ir;
@@ -57,8 +73,23 @@ __device__ __forceinline__ PrimD prim_at(const T* __restrict__ Q, const Grid& g,
   return s;
 }
 
-// Resolved velocity and temperature gradients at o: central differences
-// along the three index directions and the chain rule with the metrics.
+// Velocity and temperature gradients at o from the central differences
+// dl[d] of (u, v, w, T) along the three index directions (chain rule with
+// the metrics of o).
+template <typename T>
+__device__ __forceinline__ void chain_rule(const double dl[3][4], const T* __restrict__ M,
+                                           const Grid& g, int o, double gu[3][3], double gT[3]) {
+  const double iV = trcp((double)M[9LL * g.vs + o]);
+  for (int m = 0; m < 3; ++m) {
+    const double S0 = (double)M[(long long)m * g.vs + o];
+    const double S1 = (double)M[(long long)(3 + m) * g.vs + o];
+    const double S2 = (double)M[(long long)(6 + m) * g.vs + o];
+    for (int f = 0; f < 3; ++f) gu[f][m] = (S0 * dl[0][f] + S1 * dl[1][f] + S2 * dl[2][f]) * iV;
+    gT[m] = (S0 * dl[0][3] + S1 * dl[1][3] + S2 * dl[2][3]) * iV;
+  }
+}
+
+// Resolved gradients at o, the neighbours' primitives from global memory.
 template <typename T>
 __device__ __forceinline__ void gradients(const T* __restrict__ Q, const T* __restrict__ M,
                                           const Grid& g, int o, double gamma, double gu[3][3],
@@ -72,14 +103,7 @@ __device__ __forceinline__ void gradients(const T* __restrict__ Q, const T* __re
     dl[d][2] = 0.5 * (a.w - b.w);
     dl[d][3] = 0.5 * (a.T - b.T);
   }
-  const double iV = 1.0 / (double)M[9LL * g.vs + o];
-  for (int m = 0; m < 3; ++m) {
-    const double S0 = (double)M[(long long)m * g.vs + o];
-    const double S1 = (double)M[(long long)(3 + m) * g.vs + o];
-    const double S2 = (double)M[(long long)(6 + m) * g.vs + o];
-    for (int f = 0; f < 3; ++f) gu[f][m] = (S0 * dl[0][f] + S1 * dl[1][f] + S2 * dl[2][f]) * iV;
-    gT[m] = (S0 * dl[0][3] + S1 * dl[1][3] + S2 * dl[2][3]) * iV;
-  }
+  chain_rule(dl, M, g, o, gu, gT);
 }
 
 __device__ __forceinline__ void strain(const double gu[3][3], double S[3][3], double& Smag) {
@@ -89,37 +113,95 @@ __device__ __forceinline__ void strain(const double gu[3][3], double S[3][3], do
       S[i][j] = 0.5 * (gu[i][j] + gu[j][i]);
       s2 += S[i][j] * S[i][j];
     }
-  Smag = sqrt(2.0 * s2);
+  Smag = tsqrt(2.0 * s2);
 }
 
-// The 27-point product filter (weights FW[a] FW[b] FW[c], the separable
-// three-point filter along i, j and k) of NF fields at o, accumulated point
-// by point (few live registers); `val(o, v)` gives the fields at o.
-template <int NF, typename F>
-__device__ __forceinline__ void filter27(const Grid& g, int o, F val, double out[NF]) {
-  for (int f = 0; f < NF; ++f) out[f] = 0.0;
-  // few fields: unrolled (loads in flight together); many: rolled (registers)
-  constexpr int U = NF <= 5 ? 3 : 1;
-#pragma unroll U
-  for (int dk = 0; dk < 3; ++dk)
-#pragma unroll U
-    for (int dj = 0; dj < 3; ++dj) {
-      const double wjk = FW[dk] * FW[dj];
-      const int ob = o + (dk - 1) * g.plane + (dj - 1) * g.pitch;
-#pragma unroll
-      for (int di = 0; di < 3; ++di) {
-        double v[NF];
-        val(ob + di - 1, v);
-        const double w = wjk * FW[di];
-        for (int f = 0; f < NF; ++f) out[f] += w * v[f];
-      }
-    }
-}
+// Tiles of the columns [-1, n] x [-1, n] of a plane; every padded plane.
+// Raw fields on the tile and a one-point ring (DP_*), primitives on the tile
+// and a two-point ring (DQ_*).
+constexpr int DP_X = 16, DP_Y = 16, DP_HX = DP_X + 2, DP_HY = DP_Y + 2, DP_HP = DP_HX * DP_HY;
+constexpr int DQ_HX = DP_X + 4, DQ_HY = DP_Y + 4, DQ_HP = DQ_HX * DQ_HY;
 
 template <typename T>
-__global__ __launch_bounds__(DY_BS) void k_dyn_fields(const T* __restrict__ Q,
-                                                      const T* __restrict__ M, Grid g,
-                                                      double gamma, double* __restrict__ SC) {
+__global__ __launch_bounds__(DP_X * DP_Y) void k_dyn_plane(const T* __restrict__ Q,
+                                                           const T* __restrict__ M, Grid g,
+                                                           double gamma, int tiles_x,
+                                                           double* __restrict__ SC) {
+  __shared__ double sF[DY_NF][DP_HP];
+  __shared__ double sP[5][DQ_HP];     // rho, u, v, w, T
+  const int i0 = (blockIdx.x % tiles_x) * DP_X - 1, j0 = (blockIdx.x / tiles_x) * DP_Y - 1;
+  const int k = (int)blockIdx.y - NG;
+  // the gradient fields are needed on the planes [-1, n] (uniform per block)
+  const bool kgrad = k >= -1 && k <= g.nth;
+  const int tid = threadIdx.x;
+  // primitives of the tile and two rings, clamped to the padded box (a
+  // clamped slot feeds no stored value)
+  for (int e = tid; e < DQ_HP; e += DP_X * DP_Y) {
+    const int i = min(i0 - 2 + e % DQ_HX, g.nx + 1), j = min(j0 - 2 + e / DQ_HX, g.nr + 1);
+    const PrimD s = prim_at(Q, g, g.at(max(i, -NG), max(j, -NG), k), gamma);
+    sP[0][e] = s.rho;
+    sP[1][e] = s.u;
+    sP[2][e] = s.v;
+    sP[3][e] = s.w;
+    sP[4][e] = s.T;
+  }
+  __syncthreads();
+  const int IJ[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+  for (int e = tid; e < DP_HP; e += DP_X * DP_Y) {
+    const int hx = e % DP_HX, hy = e / DP_HX;
+    const int i = i0 - 1 + hx, j = j0 - 1 + hy;
+    const int ep = (hy + 1) * DQ_HX + hx + 1;           // the same point among the primitives
+    double F[DY_NF];
+    const double rho = sP[0][ep], uu[3] = {sP[1][ep], sP[2][ep], sP[3][ep]}, Tt = sP[4][ep];
+    F[DY_R] = rho;
+    for (int c = 0; c < 3; ++c) F[DY_R + 1 + c] = rho * uu[c];
+    F[DY_R + 4] = rho * Tt;
+    // the other fields only where an interior point's filter reads them
+    if (kgrad && i >= -1 && i <= g.nx && j >= -1 && j <= g.nr) {
+      for (int q = 0; q < 6; ++q) F[DY_PUU + q] = rho * uu[IJ[q][0]] * uu[IJ[q][1]];
+      for (int c = 0; c < 3; ++c) F[DY_PUT + c] = rho * uu[c] * Tt;
+      const int o = g.at(i, j, k);
+      double dl[3][4];
+      const int sd[2] = {1, DQ_HX};
+      for (int d = 0; d < 2; ++d)
+        for (int f = 0; f < 4; ++f) dl[d][f] = 0.5 * (sP[1 + f][ep + sd[d]] - sP[1 + f][ep - sd[d]]);
+      const PrimD a = prim_at(Q, g, o + g.plane, gamma), b = prim_at(Q, g, o - g.plane, gamma);
+      dl[2][0] = 0.5 * (a.u - b.u);
+      dl[2][1] = 0.5 * (a.v - b.v);
+      dl[2][2] = 0.5 * (a.w - b.w);
+      dl[2][3] = 0.5 * (a.T - b.T);
+      double gu[3][3], gT[3], S[3][3], Smag;
+      chain_rule(dl, M, g, o, gu, gT);
+      strain(gu, S, Smag);
+      const double rS = rho * Smag;
+      for (int q = 0; q < 6; ++q) F[DY_FS + q] = rS * S[IJ[q][0]][IJ[q][1]];
+      F[DY_FS2] = rho * Smag * Smag;
+      for (int m = 0; m < 3; ++m) F[DY_FT + m] = rS * gT[m];
+    } else {
+      for (int f = 0; f < DY_NG; ++f) F[f] = 0.0;
+    }
+    for (int f = 0; f < DY_NF; ++f) sF[f][e] = F[f];
+  }
+  __syncthreads();
+  const int tx = tid % DP_X, ty = tid / DP_X;
+  const int i = i0 + tx, j = j0 + ty;
+  if (i > g.nx || j > g.nr) return;
+  const int o = g.at(i, j, k);
+  const bool inner_col = i >= 0 && i < g.nx && j >= 0 && j < g.nr && kgrad;
+  const int f0 = inner_col ? 0 : DY_R;
+  for (int f = f0; f < DY_NF; ++f) {
+    double acc = 0.0;
+    for (int b = 0; b < 3; ++b) {
+      const int e = (ty + b) * DP_HX + tx;
+      acc += FW[b] * (FW[0] * sF[f][e] + FW[1] * sF[f][e + 1] + FW[2] * sF[f][e + 2]);
+    }
+    SC[(long long)f * g.vs + o] = acc;
+  }
+}
+
+// hat(rho), hat(rho u_i), hat(rho T) at the points of [-1, n]^3: the
+// i-j-filtered fields filtered along k.
+__global__ __launch_bounds__(DY_BS) void k_dyn_hat(Grid g, double* __restrict__ SC) {
   const int NX1 = g.nx + 2, NR1 = g.nr + 2, NT1 = g.nth + 2;
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= (long long)NX1 * NR1 * NT1) return;
@@ -127,24 +209,11 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_fields(const T* __restrict__ Q,
   const int j = (int)((t / NX1) % NR1) - 1;
   const int k = (int)(t / ((long long)NX1 * NR1)) - 1;
   const int o = g.at(i, j, k);
-  double gu[3][3], gT[3], S[3][3], Smag;
-  gradients(Q, M, g, o, gamma, gu, gT);
-  strain(gu, S, Smag);
-  const double rho = (double)Q[o];
-  const double rS = rho * Smag;
-  const int IJ[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
-  for (int q = 0; q < 6; ++q) SC[(long long)(DY_FS + q) * g.vs + o] = rS * S[IJ[q][0]][IJ[q][1]];
-  SC[(long long)DY_FS2 * g.vs + o] = rho * Smag * Smag;
-  for (int m = 0; m < 3; ++m) SC[(long long)(DY_FT + m) * g.vs + o] = rS * gT[m];
-  // hat(rho), hat(rho u_i), hat(rho T) over the padded box
-  double h[5];
-  filter27<5>(g, o, [&](int oo, double v[5]) {
-    const PrimD s = prim_at(Q, g, oo, gamma);
-    v[0] = s.rho; v[1] = s.rho * s.u; v[2] = s.rho * s.v; v[3] = s.rho * s.w; v[4] = s.rho * s.T;
-  }, h);
-  SC[(long long)DY_HR * g.vs + o] = h[0];
-  for (int c = 0; c < 3; ++c) SC[(long long)(DY_HRU + c) * g.vs + o] = h[1 + c];
-  SC[(long long)DY_HRT * g.vs + o] = h[4];
+  for (int f = 0; f < 5; ++f) {
+    const double* F = SC + (long long)(DY_R + f) * g.vs;
+    SC[(long long)(DY_HR + f) * g.vs + o] =
+        FW[0] * F[o - g.plane] + FW[1] * F[o] + FW[2] * F[o + g.plane];
+  }
 }
 
 template <typename T>
@@ -153,35 +222,31 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_sums(const T* __restrict__ Q,
                                                     double gamma, const double* __restrict__ SC,
                                                     double* __restrict__ part) {
   __shared__ double red[DY_NSUM][DY_BS];
-  const long long tot = (long long)g.nx * g.nr * g.nth;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  // blocks of an interior plane dealt to the eight XCDs so that each XCD
+  // walks its share of every plane in order (the k-neighbour planes are then
+  // in its own L2)
+  const int P = (g.nx * g.nr + DY_BS - 1) / DY_BS, Pmax = (P + DY_NXCD - 1) / DY_NXCD;
+  const int hw = blockIdx.x, x = hw % DY_NXCD, r = hw / DY_NXCD;
+  const int k = r / Pmax, pb = x * Pmax + r % Pmax;
+  const int q0 = pb * DY_BS + (int)threadIdx.x;
   double term[DY_NSUM] = {0, 0, 0, 0, 0, 0, 0};
-  if (t < tot) {
-    const int i = (int)(t % g.nx);
-    const int j = (int)((t / g.nx) % g.nr);
-    const int k = (int)(t / ((long long)g.nx * g.nr));
+  if (k < g.nth && pb < P && q0 < g.nx * g.nr) {
+    const int i = q0 % g.nx, j = q0 / g.nx;
     const int o = g.at(i, j, k);
     // resolved strain and temperature gradient at the point
     double gu[3][3], gT[3], S[3][3], Smag;
     gradients(Q, M, g, o, gamma, gu, gT);
     strain(gu, S, Smag);
     const double trS = S[0][0] + S[1][1] + S[2][2];
-    // filtered fields from [-1, n]^3
-    double hF[10];
-    filter27<10>(g, o, [&](int oo, double v[10]) {
-      for (int q = 0; q < 10; ++q) v[q] = SC[(long long)q * g.vs + oo];
-    }, hF);
-    // filtered products of the padded state
-    double hP[9];
-    filter27<9>(g, o, [&](int oo, double v[9]) {
-      const PrimD s = prim_at(Q, g, oo, gamma);
-      const double uu[3] = {s.u, s.v, s.w};
-      v[0] = s.rho * uu[0] * uu[0]; v[1] = s.rho * uu[1] * uu[1]; v[2] = s.rho * uu[2] * uu[2];
-      v[3] = s.rho * uu[0] * uu[1]; v[4] = s.rho * uu[0] * uu[2]; v[5] = s.rho * uu[1] * uu[2];
-      for (int c = 0; c < 3; ++c) v[6 + c] = s.rho * uu[c] * s.T;
-    }, hP);
+    // the other filtered fields: the i-j-filtered ones filtered along k
+    double hF[DY_PUU], hP[DY_NG - DY_PUU];
+    for (int f = 0; f < DY_NG; ++f) {
+      const double* F = SC + (long long)f * g.vs;
+      const double v = FW[0] * F[o - g.plane] + FW[1] * F[o] + FW[2] * F[o + g.plane];
+      if (f < DY_PUU) hF[f] = v; else hP[f - DY_PUU] = v;
+    }
     const double hr = SC[(long long)DY_HR * g.vs + o];
-    const double ihr = 1.0 / hr;
+    const double ihr = trcp(hr);
     double hru[3];
     for (int c = 0; c < 3; ++c) hru[c] = SC[(long long)(DY_HRU + c) * g.vs + o];
     const double hrT = SC[(long long)DY_HRT * g.vs + o];
@@ -191,15 +256,15 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_sums(const T* __restrict__ Q,
     double dl[3][4];
     for (int d = 0; d < 3; ++d) {
       const int op = o + step[d], om = o - step[d];
-      const double irp = 1.0 / SC[(long long)DY_HR * g.vs + op];
-      const double irm = 1.0 / SC[(long long)DY_HR * g.vs + om];
+      const double irp = trcp(SC[(long long)DY_HR * g.vs + op]);
+      const double irm = trcp(SC[(long long)DY_HR * g.vs + om]);
       for (int c = 0; c < 3; ++c)
         dl[d][c] = 0.5 * (SC[(long long)(DY_HRU + c) * g.vs + op] * irp -
                           SC[(long long)(DY_HRU + c) * g.vs + om] * irm);
       dl[d][3] = 0.5 * (SC[(long long)DY_HRT * g.vs + op] * irp - SC[(long long)DY_HRT * g.vs + om] * irm);
     }
     const double V = (double)M[9LL * g.vs + o];
-    const double iV = 1.0 / V;
+    const double iV = trcp(V);
     double guh[3][3], gTh[3];
     for (int m = 0; m < 3; ++m) {
       const double S0 = (double)M[(long long)m * g.vs + o];
@@ -211,7 +276,8 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_sums(const T* __restrict__ Q,
     double Sh[3][3], Shmag;
     strain(guh, Sh, Shmag);
     const double trSh = Sh[0][0] + Sh[1][1] + Sh[2][2];
-    const double D2 = pow(fabs(V), 2.0 / 3.0);
+    const double cV = cbrt(fabs(V));
+    const double D2 = cV * cV;                       // Delta^2 = |J^-1|^(2/3)
     const double Dh2 = 4.0 * D2;
     // L_ij and the contractions
     const int IJ[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
@@ -288,16 +354,19 @@ __global__ __launch_bounds__(DY_BS) void k_dyn_final(const double* __restrict__ 
 }
 
 int dyn_blocks(const Grid& g) {
-  return (int)blocks_for((long long)g.nx * g.nr * g.nth, DY_BS);
+  const int P = (g.nx * g.nr + DY_BS - 1) / DY_BS;
+  return DY_NXCD * ((P + DY_NXCD - 1) / DY_NXCD) * g.nth;
 }
 
 template <typename T>
 hipError_t launch_dynamic(const T* Q, const T* M, const Grid& g, double gamma, double Cv,
                           double Pr_static, double* SC, double* part, double* dyn,
                           hipStream_t s) {
+  const int tiles_x = (g.nx + 2 + DP_X - 1) / DP_X, tiles_y = (g.nr + 2 + DP_Y - 1) / DP_Y;
+  hipLaunchKernelGGL(k_dyn_plane<T>, dim3(tiles_x * tiles_y, g.nth + 2 * NG), dim3(DP_X * DP_Y), 0, s,
+                     Q, M, g, gamma, tiles_x, SC);
   const long long n1 = (long long)(g.nx + 2) * (g.nr + 2) * (g.nth + 2);
-  hipLaunchKernelGGL(k_dyn_fields<T>, dim3(blocks_for(n1, DY_BS)), dim3(DY_BS), 0, s, Q, M, g,
-                     gamma, SC);
+  hipLaunchKernelGGL(k_dyn_hat, dim3(blocks_for(n1, DY_BS)), dim3(DY_BS), 0, s, g, SC);
   const int nb = dyn_blocks(g);
   hipLaunchKernelGGL(k_dyn_sums<T>, dim3(nb), dim3(DY_BS), 0, s, Q, M, g, gamma,
                      (const double*)SC, part);

@@ -43,7 +43,7 @@ hipError_t launch_fused(const T* Q, const T* M, const Grid& g, const Phys<T>& ph
 // (DYN_SCRATCH_VARS padded FP64 variables), part (7 doubles per block of
 // dyn_blocks(g)), dyn (DYN_COEF_DOUBLES): [0] C_ds+ / Cv, [1] 1 / Pr_sgs,
 // [2] (2/3) C_I+, [3..5] C_I, C_ds, Pr_sgs as computed, [6..12] the sums.
-constexpr int DYN_SCRATCH_VARS = 15;
+constexpr int DYN_SCRATCH_VARS = 29;
 constexpr int DYN_COEF_DOUBLES = 16;
 int dyn_blocks(const Grid& g);
 template <typename T>

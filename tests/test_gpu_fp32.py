@@ -4,7 +4,7 @@ oracle is a precision statement, not parity: FP32 rounding of O(1) fluxes
 whose differences are O(h) smaller leaves a relative residual error of
 order 1e-6 .. 1e-4, and a state error of order N * CFL * 6e-8.
 
-Bars: residual 1e-3 (max per group), state after 10 steps 1e-5, free
+Bars: residual 1e-3 (max per group), state after 10 and after 50 steps 1e-5, free
 stream 1e-5 of the flux scale."""
 import numpy as np
 import pytest
@@ -38,7 +38,7 @@ def test_fp32_residual_error(name):
     s.close()
 
 
-@pytest.mark.parametrize("name,steps", [("box32", 10), ("jet70x33x24", 10)])
+@pytest.mark.parametrize("name,steps", [("box32", 10), ("jet70x33x24", 10), ("jet70x33x24", 50)])
 def test_fp32_state_after_steps(name, steps):
     announce("fp32-rk5", name, steps)
     pb = problems.box_problem(32) if name == "box32" else problems.jet_problem(70, 33, 24)

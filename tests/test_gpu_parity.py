@@ -4,7 +4,9 @@ span several tiles with ragged tails, plus properties at full size.
 
 Bars (FP64): metrics and copied ghosts agree to rounding (1e-14 relative);
 the residual to 1e-12 of its max per group (mass, momentum, energy); the
-state after 10 RK5 steps to 1e-11.  The GPU contracts multiply-adds and
+state after 10 RK5 steps to 1e-11, after 100 steps (the jet workload's run
+length, on a mesh the oracle steps in seconds) to 1e-10: rounding
+differences grow at most linearly with the number of steps.  The GPU contracts multiply-adds and
 uses reciprocal multiplies where the oracle divides, so agreement is to a
 few ulps of the flux scale, amplified by the cancellation in flux
 differences."""
@@ -22,6 +24,7 @@ pytestmark = pytest.mark.gpu
 
 R_BAR = 1e-12
 Q_BAR = 1e-11
+Q_BAR_100 = 1e-10
 
 
 def _oracle(pb):
@@ -121,7 +124,8 @@ def test_time_step_matches_oracle():
     s.close()
 
 
-@pytest.mark.parametrize("name,steps", [("box32", 10), ("jet37x22x20", 10), ("jet8x6x8", 4)])
+@pytest.mark.parametrize("name,steps", [("box32", 10), ("jet37x22x20", 10), ("jet8x6x8", 4),
+                                        ("jet37x22x20", 100)])
 def test_rk5_steps_match_oracle(name, steps):
     announce("rk5", name, steps)
     pb = CASES[name]()
@@ -134,7 +138,7 @@ def test_rk5_steps_match_oracle(name, steps):
     assert np.allclose(dt, dts, rtol=1e-12, atol=0)
     err = grouped_rel_err(Q, Q_ref)
     print(f"{name}: Q after {steps} steps rel err {err:.3e}")
-    assert err <= Q_BAR
+    assert err <= (Q_BAR if steps <= 10 else Q_BAR_100)
     s.close()
 
 

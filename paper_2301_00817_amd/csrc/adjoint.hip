@@ -108,10 +108,11 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
                                                   double* __restrict__ SC) {
   int kk, pb;
   if (!plane_block(g, pm, kk, pb)) return;
-  const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
+  // whole rows of the padded plane (the pitch), so that stores fill lines
   const int q0 = pb * 256 + threadIdx.x;
-  if (q0 >= NX * NR) return;
-  const int i = q0 % NX - NG, j = q0 / NX - NG, k = kk - NG;
+  if (q0 >= g.plane) return;
+  const int i = q0 % g.pitch - NG, j = q0 / g.pitch - NG, k = kk - NG;
+  if (i >= g.nx + NG) return;
   const int o = g.at(i, j, k);
   double q[5], pr[5];
   load5d(Q, g, o, q);
@@ -731,7 +732,7 @@ hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
                                const Phys<double>& ph, const int bc[6], const double ref_prim[5],
                                double p_exit, const double* inflow, const double* Rb, double* SC,
                                double* Qb, double* inflow_bar, hipStream_t s) {
-  const PlaneMap ppm = plane_map(((g.nx + 2 * NG) * (g.nr + 2 * NG) + 255) / 256);
+  const PlaneMap ppm = plane_map((g.plane + 255) / 256);
   hipLaunchKernelGGL(k_adj_prep, dim3(plane_map_grid(ppm, g)), dim3(256), 0, s, Q, M, g, ph, ppm, SC);
   const int tiles_x = (g.nx + 2 * NG + AT_X - 1) / AT_X;
   const PlaneMap tpm = plane_map(tiles_x * ((g.nr + 2 * NG + AT_Y - 1) / AT_Y));

@@ -8,12 +8,13 @@
 // fixed-order trees (reproducible).
 //
 // The separable filter is applied one direction at a time:
-//   k_dyn_plane   per 16 x 16 tile of a plane: the raw fields of the tile
-//                 and a one-point ring (rho |S| S_ij, rho |S|^2,
-//                 rho |S| dT/dx_j from central differences and the chain
-//                 rule; rho u_i u_j, rho u_i T; rho, rho u_i, rho T) formed
-//                 once per point into LDS, filtered along i and j there and
-//                 stored;
+//   k_dyn_plane   per 16 x 16 tile of a plane, the primitives of the tile
+//                 and two rings staged once in LDS: rho |S| S_ij,
+//                 rho |S|^2, rho |S| dT/dx_j (central differences and the
+//                 chain rule) formed once per point of the tile and its ring
+//                 into LDS; rho, rho u_i, rho T, rho u_i u_j, rho u_i T
+//                 formed from the staged primitives where read; all filtered
+//                 along i and j and stored;
 //   k_dyn_hat     points of [-1, n]^3: the filter along k of rho, rho u_i,
 //                 rho T -> hat(rho), hat(rho u_i), hat(rho T);
 //   k_dyn_sums    interior points: the filter along k of the other fields,
@@ -116,9 +117,9 @@ __device__ __forceinline__ void strain(const double gu[3][3], double S[3][3], do
   Smag = tsqrt(2.0 * s2);
 }
 
-// Tiles of the columns [-1, n] x [-1, n] of a plane; every padded plane.
-// Raw fields on the tile and a one-point ring (DP_*), primitives on the tile
-// and a two-point ring (DQ_*).
+// Tiles of the columns [-2, n] x [-1, n] of a plane; every padded plane.
+// Gradient fields on the tile and a one-point ring (DP_*), primitives on the
+// tile and a two-point ring (DQ_*).
 constexpr int DP_X = 16, DP_Y = 16, DP_HX = DP_X + 2, DP_HY = DP_Y + 2, DP_HP = DP_HX * DP_HY;
 constexpr int DQ_HX = DP_X + 4, DQ_HY = DP_Y + 4, DQ_HP = DQ_HX * DQ_HY;
 
@@ -127,9 +128,11 @@ __global__ __launch_bounds__(DP_X * DP_Y) void k_dyn_plane(const T* __restrict__
                                                            const T* __restrict__ M, Grid g,
                                                            double gamma, int tiles_x,
                                                            double* __restrict__ SC) {
-  __shared__ double sF[DY_NF][DP_HP];
-  __shared__ double sP[5][DQ_HP];     // rho, u, v, w, T
-  const int i0 = (blockIdx.x % tiles_x) * DP_X - 1, j0 = (blockIdx.x / tiles_x) * DP_Y - 1;
+  __shared__ double sP[5][DQ_HP];          // rho, u, v, w, T
+  __shared__ double sG[DY_PUU][DP_HP];     // rho |S| S_ij, rho |S|^2, rho |S| dT/dx_j
+  // tile columns start at padded index 0 (i = -2) so that each tile row is
+  // whole 128-byte lines of the scratch arrays
+  const int i0 = (blockIdx.x % tiles_x) * DP_X - NG, j0 = (blockIdx.x / tiles_x) * DP_Y - 1;
   const int k = (int)blockIdx.y - NG;
   // the gradient fields are needed on the planes [-1, n] (uniform per block)
   const bool kgrad = k >= -1 && k <= g.nth;
@@ -147,67 +150,86 @@ __global__ __launch_bounds__(DP_X * DP_Y) void k_dyn_plane(const T* __restrict__
   }
   __syncthreads();
   const int IJ[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
-  for (int e = tid; e < DP_HP; e += DP_X * DP_Y) {
-    const int hx = e % DP_HX, hy = e / DP_HX;
-    const int i = i0 - 1 + hx, j = j0 - 1 + hy;
-    const int ep = (hy + 1) * DQ_HX + hx + 1;           // the same point among the primitives
-    double F[DY_NF];
-    const double rho = sP[0][ep], uu[3] = {sP[1][ep], sP[2][ep], sP[3][ep]}, Tt = sP[4][ep];
-    F[DY_R] = rho;
-    for (int c = 0; c < 3; ++c) F[DY_R + 1 + c] = rho * uu[c];
-    F[DY_R + 4] = rho * Tt;
-    // the other fields only where an interior point's filter reads them
-    if (kgrad && i >= -1 && i <= g.nx && j >= -1 && j <= g.nr) {
-      for (int q = 0; q < 6; ++q) F[DY_PUU + q] = rho * uu[IJ[q][0]] * uu[IJ[q][1]];
-      for (int c = 0; c < 3; ++c) F[DY_PUT + c] = rho * uu[c] * Tt;
-      const int o = g.at(i, j, k);
-      double dl[3][4];
-      const int sd[2] = {1, DQ_HX};
-      for (int d = 0; d < 2; ++d)
-        for (int f = 0; f < 4; ++f) dl[d][f] = 0.5 * (sP[1 + f][ep + sd[d]] - sP[1 + f][ep - sd[d]]);
-      const PrimD a = prim_at(Q, g, o + g.plane, gamma), b = prim_at(Q, g, o - g.plane, gamma);
-      dl[2][0] = 0.5 * (a.u - b.u);
-      dl[2][1] = 0.5 * (a.v - b.v);
-      dl[2][2] = 0.5 * (a.w - b.w);
-      dl[2][3] = 0.5 * (a.T - b.T);
-      double gu[3][3], gT[3], S[3][3], Smag;
-      chain_rule(dl, M, g, o, gu, gT);
-      strain(gu, S, Smag);
-      const double rS = rho * Smag;
-      for (int q = 0; q < 6; ++q) F[DY_FS + q] = rS * S[IJ[q][0]][IJ[q][1]];
-      F[DY_FS2] = rho * Smag * Smag;
-      for (int m = 0; m < 3; ++m) F[DY_FT + m] = rS * gT[m];
-    } else {
-      for (int f = 0; f < DY_NG; ++f) F[f] = 0.0;
+  if (kgrad) {
+    for (int e = tid; e < DP_HP; e += DP_X * DP_Y) {
+      const int hx = e % DP_HX, hy = e / DP_HX;
+      const int i = i0 - 1 + hx, j = j0 - 1 + hy;
+      double F[DY_PUU];
+      // only where an interior column's filter reads them
+      if (i >= -1 && i <= g.nx && j >= -1 && j <= g.nr) {
+        const int ep = (hy + 1) * DQ_HX + hx + 1;       // the same point among the primitives
+        const int o = g.at(i, j, k);
+        double dl[3][4];
+        const int sd[2] = {1, DQ_HX};
+        for (int d = 0; d < 2; ++d)
+          for (int f = 0; f < 4; ++f) dl[d][f] = 0.5 * (sP[1 + f][ep + sd[d]] - sP[1 + f][ep - sd[d]]);
+        const PrimD a = prim_at(Q, g, o + g.plane, gamma), b = prim_at(Q, g, o - g.plane, gamma);
+        dl[2][0] = 0.5 * (a.u - b.u);
+        dl[2][1] = 0.5 * (a.v - b.v);
+        dl[2][2] = 0.5 * (a.w - b.w);
+        dl[2][3] = 0.5 * (a.T - b.T);
+        double gu[3][3], gT[3], S[3][3], Smag;
+        chain_rule(dl, M, g, o, gu, gT);
+        strain(gu, S, Smag);
+        const double rho = sP[0][ep], rS = rho * Smag;
+        for (int q = 0; q < 6; ++q) F[DY_FS + q] = rS * S[IJ[q][0]][IJ[q][1]];
+        F[DY_FS2] = rho * Smag * Smag;
+        for (int m = 0; m < 3; ++m) F[DY_FT + m] = rS * gT[m];
+      } else {
+        for (int f = 0; f < DY_PUU; ++f) F[f] = 0.0;
+      }
+      for (int f = 0; f < DY_PUU; ++f) sG[f][e] = F[f];
     }
-    for (int f = 0; f < DY_NF; ++f) sF[f][e] = F[f];
+    __syncthreads();
   }
-  __syncthreads();
   const int tx = tid % DP_X, ty = tid / DP_X;
   const int i = i0 + tx, j = j0 + ty;
   if (i > g.nx || j > g.nr) return;
   const int o = g.at(i, j, k);
   const bool inner_col = i >= 0 && i < g.nx && j >= 0 && j < g.nr && kgrad;
-  const int f0 = inner_col ? 0 : DY_R;
-  for (int f = f0; f < DY_NF; ++f) {
-    double acc = 0.0;
+  // the state fields and the products, formed from the staged primitives
+  // where the filter reads them
+  double acc[DY_NF - DY_PUU];
+  for (int f = 0; f < DY_NF - DY_PUU; ++f) acc[f] = 0.0;
+  for (int b = 0; b < 3; ++b) {
+    double row[DY_NF - DY_PUU];
+    for (int f = 0; f < DY_NF - DY_PUU; ++f) row[f] = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const int e = (ty + 1 + b) * DQ_HX + tx + 1 + a;
+      const double rho = sP[0][e], uu[3] = {sP[1][e], sP[2][e], sP[3][e]}, Tt = sP[4][e];
+      row[DY_R - DY_PUU] += FW[a] * rho;
+      for (int c = 0; c < 3; ++c) row[DY_R - DY_PUU + 1 + c] += FW[a] * (rho * uu[c]);
+      row[DY_R - DY_PUU + 4] += FW[a] * (rho * Tt);
+      if (inner_col) {
+        for (int q = 0; q < 6; ++q) row[q] += FW[a] * (rho * uu[IJ[q][0]] * uu[IJ[q][1]]);
+        for (int c = 0; c < 3; ++c) row[DY_PUT - DY_PUU + c] += FW[a] * (rho * uu[c] * Tt);
+      }
+    }
+    for (int f = 0; f < DY_NF - DY_PUU; ++f) acc[f] += FW[b] * row[f];
+  }
+  for (int f = inner_col ? DY_PUU : DY_R; f < DY_NF; ++f) SC[(long long)f * g.vs + o] = acc[f - DY_PUU];
+  if (!inner_col) return;
+  for (int f = 0; f < DY_PUU; ++f) {
+    double sum = 0.0;
     for (int b = 0; b < 3; ++b) {
       const int e = (ty + b) * DP_HX + tx;
-      acc += FW[b] * (FW[0] * sF[f][e] + FW[1] * sF[f][e + 1] + FW[2] * sF[f][e + 2]);
+      sum += FW[b] * (FW[0] * sG[f][e] + FW[1] * sG[f][e + 1] + FW[2] * sG[f][e + 2]);
     }
-    SC[(long long)f * g.vs + o] = acc;
+    SC[(long long)f * g.vs + o] = sum;
   }
 }
 
 // hat(rho), hat(rho u_i), hat(rho T) at the points of [-1, n]^3: the
-// i-j-filtered fields filtered along k.
+// i-j-filtered fields filtered along k.  One thread per element of the rows
+// j in [-1, n] of the planes [-1, n] (whole rows, so stores fill lines).
 __global__ __launch_bounds__(DY_BS) void k_dyn_hat(Grid g, double* __restrict__ SC) {
-  const int NX1 = g.nx + 2, NR1 = g.nr + 2, NT1 = g.nth + 2;
+  const long long rows = (long long)(g.nr + 2) * (g.nth + 2);
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= (long long)NX1 * NR1 * NT1) return;
-  const int i = (int)(t % NX1) - 1;
-  const int j = (int)((t / NX1) % NR1) - 1;
-  const int k = (int)(t / ((long long)NX1 * NR1)) - 1;
+  if (t >= rows * g.pitch) return;
+  const int i = (int)(t % g.pitch) - NG;
+  const long long r = t / g.pitch;
+  const int j = (int)(r % (g.nr + 2)) - 1, k = (int)(r / (g.nr + 2)) - 1;
+  if (i < -1 || i > g.nx) return;
   const int o = g.at(i, j, k);
   for (int f = 0; f < 5; ++f) {
     const double* F = SC + (long long)(DY_R + f) * g.vs;
@@ -362,11 +384,11 @@ template <typename T>
 hipError_t launch_dynamic(const T* Q, const T* M, const Grid& g, double gamma, double Cv,
                           double Pr_static, double* SC, double* part, double* dyn,
                           hipStream_t s) {
-  const int tiles_x = (g.nx + 2 + DP_X - 1) / DP_X, tiles_y = (g.nr + 2 + DP_Y - 1) / DP_Y;
+  const int tiles_x = (g.nx + 3 + DP_X - 1) / DP_X, tiles_y = (g.nr + 2 + DP_Y - 1) / DP_Y;
   hipLaunchKernelGGL(k_dyn_plane<T>, dim3(tiles_x * tiles_y, g.nth + 2 * NG), dim3(DP_X * DP_Y), 0, s,
                      Q, M, g, gamma, tiles_x, SC);
-  const long long n1 = (long long)(g.nx + 2) * (g.nr + 2) * (g.nth + 2);
-  hipLaunchKernelGGL(k_dyn_hat, dim3(blocks_for(n1, DY_BS)), dim3(DY_BS), 0, s, g, SC);
+  const long long nrow = (long long)(g.nr + 2) * (g.nth + 2) * g.pitch;
+  hipLaunchKernelGGL(k_dyn_hat, dim3(blocks_for(nrow, DY_BS)), dim3(DY_BS), 0, s, g, SC);
   const int nb = dyn_blocks(g);
   hipLaunchKernelGGL(k_dyn_sums<T>, dim3(nb), dim3(DY_BS), 0, s, Q, M, g, gamma,
                      (const double*)SC, part);

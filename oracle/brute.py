@@ -430,6 +430,113 @@ class Brute:
         return cur
 
 
+    def dynamic_sums(self, Q):
+        """The seven J^-1-weighted interior sums of the dynamic model
+        (subsection "Dynamic Smagorinsky Model", readings D1-D6): N_I, D_I
+        (C_I = N_I / D_I), A, B, D_d (C_ds = (A + C_I+ B) / D_d), N_P, D_P
+        (Pr_sgs = C_ds+ N_P / D_P), and for each the sum of the absolute
+        values of its terms.  The test filter is the explicit 27-point
+        product of (1/4, 1/2, 1/4) weights."""
+        S = self.fill(Q)
+        nx, nr, nth = self.n
+        wt = (0.25, 0.5, 0.25)
+        offs = [(a, b, c) for c in (-1, 0, 1) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+
+        def hat(fn, p, nf):
+            tot = [0.0] * nf
+            for a, b, c in offs:
+                w = wt[a + 1] * wt[b + 1] * wt[c + 1]
+                v = fn((p[0] + a, p[1] + b, p[2] + c))
+                tot = [t + w * x for t, x in zip(tot, v)]
+            return tot
+
+        res = {}
+
+        def resolved(p):
+            """strain S_ij, |S|, grad T and the point values at p."""
+            if p not in res:
+                gr = self.gradients(S, p)
+                g = [gr["u"], gr["v"], gr["w"]]
+                Sij = [[0.5 * (g[i][j] + g[j][i]) for j in range(3)] for i in range(3)]
+                Smag = math.sqrt(2.0 * sum(Sij[i][j] ** 2 for i in range(3) for j in range(3)))
+                res[p] = (Sij, Smag, gr["T"], self.point(S, p))
+            return res[p]
+
+        def model_fields(p):
+            """rho |S| S_ij (9), rho |S|^2, rho |S| dT/dx_j (3) at p."""
+            Sij, Smag, gT, P = resolved(p)
+            r = P["rho"]
+            return ([r * Smag * Sij[i][j] for i in range(3) for j in range(3)]
+                    + [r * Smag * Smag] + [r * Smag * gT[j] for j in range(3)])
+
+        def state_fields(p):
+            """rho, rho u_i, rho T, rho u_i u_j (9), rho u_j T (3) at p."""
+            P = self.point(S, p)
+            r, U = P["rho"], (P["u"], P["v"], P["w"])
+            return ([r] + [r * U[i] for i in range(3)] + [r * P["T"]]
+                    + [r * U[i] * U[j] for i in range(3) for j in range(3)]
+                    + [r * U[j] * P["T"] for j in range(3)])
+
+        hs = {}
+
+        def hat_state(p):
+            if p not in hs:
+                hs[p] = hat(state_fields, p, 17)
+            return hs[p]
+
+        keys = ("N_I", "D_I", "A", "B", "D_d", "N_P", "D_P")
+        sums = {k: 0.0 for k in keys}
+        mags = {k: 0.0 for k in keys}
+        for k in range(nth):
+            for j in range(nr):
+                for i in range(nx):
+                    p = (i, j, k)
+                    Sm, V = self.metric(p)
+                    Sij, Smag, gT, _ = resolved(p)
+                    trS = Sij[0][0] + Sij[1][1] + Sij[2][2]
+                    hm = hat(model_fields, p, 13)
+                    hSS = [[hm[3 * i2 + j2] for j2 in range(3)] for i2 in range(3)]
+                    hS2, hST = hm[9], hm[10:13]
+                    h = hat_state(p)
+                    hr, hru, hrT = h[0], h[1:4], h[4]
+                    hruu = [[h[5 + 3 * i2 + j2] for j2 in range(3)] for i2 in range(3)]
+                    hruT = h[14:17]
+                    # gradients of u_hat = hat(rho u)/hat(rho), T_hat = hat(rho T)/hat(rho)
+                    dl = []
+                    for d in range(3):
+                        a, b = hat_state(self._shift(p, d, 1)), hat_state(self._shift(p, d, -1))
+                        dl.append([0.5 * (a[1 + f] / a[0] - b[1 + f] / b[0]) for f in range(3)]
+                                  + [0.5 * (a[4] / a[0] - b[4] / b[0])])
+                    gh = [[(Sm[0][m] * dl[0][f] + Sm[1][m] * dl[1][f] + Sm[2][m] * dl[2][f]) / V
+                           for m in range(3)] for f in range(4)]
+                    Sh = [[0.5 * (gh[i2][j2] + gh[j2][i2]) for j2 in range(3)] for i2 in range(3)]
+                    Shmag = math.sqrt(2.0 * sum(Sh[i2][j2] ** 2 for i2 in range(3) for j2 in range(3)))
+                    trSh = Sh[0][0] + Sh[1][1] + Sh[2][2]
+                    D2 = abs(V) ** (2.0 / 3.0)
+                    Dh2 = 4.0 * D2
+                    L = [[hruu[i2][j2] - hru[i2] * hru[j2] / hr for j2 in range(3)] for i2 in range(3)]
+                    Lkk = L[0][0] + L[1][1] + L[2][2]
+                    LS = sum(L[i2][j2] * Sij[i2][j2] for i2 in range(3) for j2 in range(3))
+                    hSS_S = sum(hSS[i2][j2] * Sij[i2][j2] for i2 in range(3) for j2 in range(3))
+                    hSkk = hSS[0][0] + hSS[1][1] + hSS[2][2]
+                    ShS = sum(Sh[i2][j2] * Sij[i2][j2] for i2 in range(3) for j2 in range(3))
+                    term = {
+                        "N_I": Lkk,
+                        "D_I": 2.0 * Dh2 * hr * Shmag ** 2 - 2.0 * D2 * hS2,
+                        "A": LS - trS * Lkk / 3.0,
+                        "B": trS * 2.0 * D2 * hS2 / 3.0,
+                        "D_d": 2.0 * D2 * (hSS_S - hSkk * trS / 3.0)
+                               - 2.0 * Dh2 * hr * Shmag * (ShS - trSh * trS / 3.0),
+                        "N_P": sum(D2 * hST[m] * gT[m] - Dh2 * hr * Shmag * gh[3][m] * gT[m]
+                                   for m in range(3)),
+                        "D_P": sum((hruT[m] - hru[m] * hrT / hr) * gT[m] for m in range(3)),
+                    }
+                    for kk in keys:
+                        sums[kk] += V * term[kk]
+                        mags[kk] += abs(V * term[kk])
+        return sums, mags
+
+
 class _PointArray:
     """Q[c, k, j, i] view of a {(i, j, k): 5 values} dict."""
 

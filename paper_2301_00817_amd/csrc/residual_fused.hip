@@ -124,6 +124,16 @@ template <> struct PrefetchQ0<double> { static constexpr bool on = LESJET_PREF_Q
 template <> struct PrefetchQ0<float> { static constexpr bool on = LESJET_PREF_Q0_32 != 0; };
 #endif
 
+// Wave priority: the FP64 kernel (two waves per SIMD, bound by latency)
+// raises its waves' issue priority from the face phase to the end of the
+// epilogue, so that a wave that has its plane in LDS finishes the plane and
+// reaches the next plane's loads ahead of the waves still in the point
+// phase.  Measured on MI355X: 10 % less time per launch on the 5.9 M-point
+// jet (one round of blocks, two per CU for the whole launch), about 2 % on
+// meshes of 0.1 to 1 billion points; the FP32 kernel, bound by its ALUs,
+// gains nothing from it.
+template <typename T> struct WavePrio { static constexpr bool on = sizeof(T) == 8; };
+
 // Register budget: FP64 two waves per SIMD (242 VGPRs), FP32 four (128).
 template <typename T> struct FusedOcc;
 template <> struct FusedOcc<double> { static constexpr int waves = 2; };
@@ -344,6 +354,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     __syncthreads();
 
     // (c) faces
+    if (WavePrio<T>::on) __builtin_amdgcn_s_setprio(1);
     auto wload = [&](int yy, int xx, T w[5]) {      // W = Q with E replaced by E + p
 #pragma unroll
       for (int c = 0; c < 4; ++c) w[c] = sQ[c][yy][xx];
@@ -470,6 +481,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
 #pragma unroll
       for (int c = 0; c < 5; ++c) acc[c] = rhs[c] - Fk[c];
     }
+    if (WavePrio<T>::on) __builtin_amdgcn_s_setprio(0);
     // keep the zeta-direction point quantities of plane kk, roll the window
 #pragma unroll
     for (int c = 0; c < 5; ++c) {

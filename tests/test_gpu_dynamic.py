@@ -1,7 +1,7 @@
 """GPU parity of the dynamic Smagorinsky model (LES_SGS_DYNAMIC) against the
 oracle: the global coefficients C_I, C_ds, Pr_sgs, the residual (fused and
 two-pass kernels), RK5 steps under both update schedules, and the FP32
-storage form.
+storage form under both schedules.
 
 Cases: multi-mode periodic boxes on which the averaged C_I and C_ds are
 positive (the eddy viscosity and the isotropic stress both act), one where
@@ -120,9 +120,11 @@ def test_rk5_steps_match_oracle(name, schedule):
     s.close()
 
 
-def test_fp32_storage():
-    announce("dynamic-fp32", "modes24_s2")
+@pytest.mark.parametrize("schedule", ["stage", "step"])
+def test_fp32_storage(schedule):
+    announce("dynamic-fp32", "modes24_s2", schedule)
     pb = _case("modes24_s2")
+    pb["params"] = dict(pb["params"], schedule=schedule)
     geo, inflow = _oracle(pb)
     R_ref = les.evaluate(pb["Q"].numpy(), geo, pb["params"], inflow)
     Q_ref, _ = les.run(pb["Q"].numpy(), geo, pb["params"], inflow, steps=3)
@@ -131,7 +133,7 @@ def test_fp32_storage():
     Qn = s.pad(pb["Q"].cuda(), dtype=torch.float64)
     s.rk5_step(Qn, 3)
     er, eq = grouped_rel_err(R, R_ref), grouped_rel_err(to_np(s.interior(Qn)), Q_ref)
-    print(f"FP32 dynamic: residual {er:.3e}, state after 3 steps {eq:.3e}")
+    print(f"FP32 dynamic ({schedule}): residual {er:.3e}, state after 3 steps {eq:.3e}")
     assert er <= 1e-3 and eq <= 1e-5
     s.close()
 

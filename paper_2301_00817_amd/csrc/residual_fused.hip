@@ -80,27 +80,22 @@ template <> struct FaceOnce<float> { static constexpr bool on = LESJET_FACE_ONCE
 template <typename T>
 __device__ __forceinline__ void load_q(const T* __restrict__ Q, const Grid& g, int i, int j, int k,
                                        T q[5]) {
-  if (i >= -NG && i < g.nx + NG && j >= -NG && j < g.nr + NG) {
-    const int o = g.at(i, j, k);
+  // outside the padded box the nearest point of it is read: a finite state
+  // that no output uses (clamping instead of a default value spares the
+  // moves that would set the default before every load)
+  const int o = g.at(min(max(i, -NG), g.nx + NG - 1), min(max(j, -NG), g.nr + NG - 1), k);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) q[c] = Q[(long long)c * g.vs + o];
-  } else {
-    // outside the padded box: a harmless finite state, never used by an output
-    q[0] = T(1); q[1] = T(0); q[2] = T(0); q[3] = T(0); q[4] = T(2.5);
-  }
+  for (int c = 0; c < 5; ++c) q[c] = Q[(long long)c * g.vs + o];
 }
 
 template <typename T>
 __device__ __forceinline__ void load_metrics(const T* __restrict__ M, const Grid& g, int i, int j,
-                                             int k, bool ok, T m[10]) {
-  if (ok) {
-    const int o = g.at(i, j, k);
+                                             int k, T m[10]) {
+  // columns beyond [-1, n] (no output needs them) read the nearest column of
+  // that range: finite metrics, no default values to set
+  const int o = g.at(min(max(i, -1), g.nx), min(max(j, -1), g.nr), k);
 #pragma unroll
-    for (int c = 0; c < 10; ++c) m[c] = M[(long long)c * g.vs + o];
-  } else {
-#pragma unroll
-    for (int c = 0; c < 10; ++c) m[c] = (c == 0 || c == 4 || c == 8 || c == 9) ? T(1) : T(0);
-  }
+  for (int c = 0; c < 10; ++c) m[c] = M[(long long)c * g.vs + o];
 }
 
 // Workgroups are dealt to the eight XCDs (each with its own L2) in turn.  The
@@ -232,13 +227,11 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   double q0p[5];         // Q^(0) at (i, j, kk-1), loaded at the top of iteration kk
   const double ad_pre = PQ0 ? alpha * (*dtp) : 0.0;
   auto load_lag = [&](int kk, T v[2]) {
-    if (col_ok) {
-      const int o = g.at(i, j, kk);
-      v[0] = visc[o];
-      v[1] = visc[(long long)g.vs + o];
-    } else {
-      v[0] = T(0); v[1] = T(0);
-    }
+    // columns beyond [-1, n] read the nearest held column (all of [-1, n]^3
+    // is written at stage 1); no output uses them
+    const int o = g.at(min(max(i, -1), g.nx), min(max(j, -1), g.nr), kk);
+    v[0] = visc[o];
+    v[1] = visc[(long long)g.vs + o];
   };
   // zeta-face state of plane kk-1 (interior columns)
   T Gz[5], lbz = 0, nuz = 0, Vz = 0;
@@ -262,7 +255,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     }
     load_q(Qin, g, i, j, k0, Qd);
     prim5(Qd, ph, Pd);
-    load_metrics(M, g, i, j, k0 - 1, col_ok, met);
+    load_metrics(M, g, i, j, k0 - 1, met);
     if (LAG == LAG_READ) load_lag(k0 - 1, lag);
   }
 #pragma unroll
@@ -289,7 +282,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     // own-column and metric loads of the next plane, in flight during (b)
     if (more) {
       if (kk + 2 <= k1 + 1) load_q(Qin, g, i, j, kk + 2, Qn);
-      load_metrics(M, g, i, j, kk + 1, col_ok, metn);
+      load_metrics(M, g, i, j, kk + 1, metn);
       if (LAG == LAG_READ) load_lag(kk + 1, lagn);
     }
     if (PQ0 && interior && kk - 1 >= k0) {

@@ -97,25 +97,30 @@ __global__ void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
                             const double* __restrict__ inflow, double gamma, int xlo, int xhi,
                             int elo, int ehi, double p_exit, BPrim<T> ref,
                             const T* __restrict__ held) {
-  const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
-  const long long nz = 2LL * NG * NX * NR, ne = 2LL * NG * NX * g.nth, nxg = 2LL * NG * g.nr * g.nth;
-  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  // 32-bit index arithmetic: the ghost points number 4 (NX NR + NX nth +
+  // nr nth), far below 2^32 for every mesh the library accepts
+  const unsigned NX = g.nx + 2 * NG, NR = g.nr + 2 * NG, nth = g.nth, nr = g.nr;
+  const unsigned nz = 2u * NG * NX * NR, ne = 2u * NG * NX * nth, nxg = 2u * NG * nr * nth;
+  unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
   int i, j, k;
   if (t < nz) {
-    i = (int)(t % NX) - NG;
-    j = (int)((t / NX) % NR) - NG;
-    const int l = (int)(t / ((long long)NX * NR));      // 0..3 -> -2, -1, nth, nth+1
-    k = l < NG ? l - NG : g.nth + (l - NG);
+    const unsigned r = t / NX;
+    i = (int)(t - r * NX) - NG;
+    const unsigned l = r / NR;                          // 0..3 -> -2, -1, nth, nth+1
+    j = (int)(r - l * NR) - NG;
+    k = l < NG ? (int)l - NG : g.nth + ((int)l - NG);
   } else if ((t -= nz) < ne) {
-    i = (int)(t % NX) - NG;
-    const int l = (int)((t / NX) % (2 * NG));
-    j = l < NG ? l - NG : g.nr + (l - NG);
-    k = (int)(t / ((long long)NX * 2 * NG));
+    const unsigned r = t / NX;
+    i = (int)(t - r * NX) - NG;
+    const unsigned l = r % (2 * NG);
+    j = l < NG ? (int)l - NG : g.nr + ((int)l - NG);
+    k = (int)(r / (2 * NG));
   } else if ((t -= ne) < nxg) {
-    const int l = (int)(t % (2 * NG));
-    i = l < NG ? l - NG : g.nx + (l - NG);
-    j = (int)((t / (2 * NG)) % g.nr);
-    k = (int)(t / (2LL * NG * g.nr));
+    const unsigned l = t % (2 * NG);
+    i = l < NG ? (int)l - NG : g.nx + ((int)l - NG);
+    const unsigned r = t / (2 * NG);
+    j = (int)(r % nr);
+    k = (int)(r / nr);
   } else {
     return;
   }

@@ -13,7 +13,7 @@
 //      then (points of [-1, n]^3) the reverse of the point function; the
 //      part of the state cotangent that depends on the point alone is
 //      finished here, the cotangents of its central differences and sensor
-//      neighbour pressures are stored.  The xi and eta lines of a 16 x 16
+//      neighbour pressures are stored.  The xi and eta lines of a 32 x 8
 //      tile are staged in LDS;
 //   3. per padded point: the neighbours' contributions through its
 //      primitives are added -> cotangent of the padded state;
@@ -361,12 +361,12 @@ __device__ __forceinline__ void point_part(const double* __restrict__ M, double*
 // alone (S_PQ) and the cotangents of p's central differences and sensor
 // neighbour pressures (S_DL, S_NC), which pass 3 hands to the neighbours.
 //
-// One block per 16 x 16 tile of a padded plane.  The block stages once, in
+// One block per 32 x 8 tile of a padded plane.  The block stages once, in
 // LDS, what the xi and eta lines of its points read (the tile and two points
 // on each side, clamped to the padded box): Rbar / J^-1, lambda_bar and nu
 // along xi and eta, J^-1, the state and the primitives.  The zeta lines and
 // the metrics come from global memory.
-constexpr int AT_X = 16, AT_Y = 16, AT_HX = AT_X + 4, AT_HY = AT_Y + 4, AT_HP = AT_HX * AT_HY;
+constexpr int AT_X = 32, AT_Y = 8, AT_HX = AT_X + 4, AT_HY = AT_Y + 4, AT_HP = AT_HX * AT_HY;
 enum { L_RT = 0, L_LB = 5, L_NU = 7, L_V = 9, L_Q = 10, L_PR = 15, L_N = 20 };
 
 struct LdsLine {

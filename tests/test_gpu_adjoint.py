@@ -140,13 +140,15 @@ def test_vjp_directional(case):
 
 
 THIN = {
-    # the main pass works on 16 x 16 tiles of the padded plane (nx + 4 by
+    # the main pass works on 32 x 8 tiles of the padded plane (nx + 4 by
     # nr + 4): many tiles along one direction and a part of one along the
-    # other, exactly two tiles along xi with one row in a second tile along
-    # eta, and the smallest box (one partial tile)
+    # other, exactly one tile along xi with one row in a third tile along
+    # eta, exactly two tiles along xi, and the smallest box (one partial
+    # tile)
     "jet300x5x6": lambda: _jet(300, 5, 6, seed=21),
     "jet5x40x6": lambda: _jet(5, 40, 6, seed=22),
     "jet28x13x8": lambda: _jet(28, 13, 8, seed=23),
+    "jet60x5x6": lambda: _jet(60, 5, 6, seed=25),
     "box5": lambda: problems.box_problem(5, seed=24, noise=1e-3),
 }
 

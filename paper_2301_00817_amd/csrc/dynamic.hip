@@ -8,7 +8,7 @@
 // fixed-order trees (reproducible).
 //
 // The separable filter is applied one direction at a time:
-//   k_dyn_plane   per 16 x 16 tile of a plane, the primitives of the tile
+//   k_dyn_plane   per 32 x 8 tile of a plane, the primitives of the tile
 //                 and two rings staged once in LDS: rho |S| S_ij,
 //                 rho |S|^2, rho |S| dT/dx_j (central differences and the
 //                 chain rule) formed once per point of the tile and its ring
@@ -120,7 +120,7 @@ __device__ __forceinline__ void strain(const double gu[3][3], double S[3][3], do
 // Tiles of the columns [-2, n] x [-1, n] of a plane; every padded plane.
 // Gradient fields on the tile and a one-point ring (DP_*), primitives on the
 // tile and a two-point ring (DQ_*).
-constexpr int DP_X = 16, DP_Y = 16, DP_HX = DP_X + 2, DP_HY = DP_Y + 2, DP_HP = DP_HX * DP_HY;
+constexpr int DP_X = 32, DP_Y = 8, DP_HX = DP_X + 2, DP_HY = DP_Y + 2, DP_HP = DP_HX * DP_HY;
 constexpr int DQ_HX = DP_X + 4, DQ_HY = DP_Y + 4, DQ_HP = DQ_HX * DQ_HY;
 
 template <typename T>

@@ -101,18 +101,33 @@ __device__ __forceinline__ bool plane_block(const Grid& g, PlaneMap pm, int& kk,
 
 // Pass 1, one thread per padded point: its pressure; for points of
 // [-1, n]^3 also 1 / J^-1, lambda_bar^d and nu^d (the face dissipation
-// coefficients, as in the point function), zero at the others.
-__global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
-                                                  const double* __restrict__ M, Grid g,
-                                                  Phys<double> ph, PlaneMap pm,
-                                                  double* __restrict__ SC) {
+// coefficients, as in the point function), zero at the others.  One block
+// per 32 x 8 tile of a padded plane (tile columns from padded index 0, so
+// that stores fill lines); the pressures of the tile and a one-point ring
+// are formed once into LDS for the sensors' xi and eta neighbours.
+constexpr int PT_X = 32, PT_Y = 8, PT_HX = PT_X + 2, PT_HP = PT_HX * (PT_Y + 2);
+
+__global__ __launch_bounds__(PT_X * PT_Y) void k_adj_prep(const double* __restrict__ Q,
+                                                          const double* __restrict__ M, Grid g,
+                                                          Phys<double> ph, PlaneMap pm,
+                                                          int tiles_x, double* __restrict__ SC) {
+  __shared__ double sp[PT_HP];
   int kk, pb;
-  if (!plane_block(g, pm, kk, pb)) return;
-  // whole rows of the padded plane (the pitch), so that stores fill lines
-  const int q0 = pb * 256 + threadIdx.x;
-  if (q0 >= g.plane) return;
-  const int i = q0 % g.pitch - NG, j = q0 / g.pitch - NG, k = kk - NG;
-  if (i >= g.nx + NG) return;
+  if (!plane_block(g, pm, kk, pb)) return;   // uniform over the block
+  const int i0 = (pb % tiles_x) * PT_X - NG, j0 = (pb / tiles_x) * PT_Y - NG, k = kk - NG;
+  for (int e = threadIdx.x; e < PT_HP; e += PT_X * PT_Y) {
+    // clamped to the padded box: a clamped slot feeds no stored value
+    const int ie = min(max(i0 - 1 + e % PT_HX, -NG), g.nx + NG - 1);
+    const int je = min(max(j0 - 1 + e / PT_HX, -NG), g.nr + NG - 1);
+    double qe[5];
+    load5d(Q, g, g.at(ie, je, k), qe);
+    sp[e] = pressure(qe, ph);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % PT_X, ty = threadIdx.x / PT_X;
+  const int i = i0 + tx, j = j0 + ty;
+  if (i >= g.nx + NG || j >= g.nr + NG) return;
+  const int slot = (ty + 1) * PT_HX + tx + 1;
   const int o = g.at(i, j, k);
   double q[5], pr[5];
   load5d(Q, g, o, q);
@@ -127,7 +142,6 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
     SC[(long long)S_IV * g.vs + o] = 0.0;
     return;
   }
-  const int step[3] = {1, g.pitch, g.plane};
   // J^-1 = 0 on the axis row of a centerline-through-the-nodes mesh: no face
   // uses its lambda_bar and its Rbar is ignored, so 0 is stored there
   const bool axis_row = ph.axis_node && j == 0;
@@ -141,10 +155,18 @@ __global__ __launch_bounds__(256) void k_adj_prep(const double* __restrict__ Q,
                  S2 = M[(long long)(3 * d + 2) * g.vs + o];
     const double Uc = S0 * pr[0] + S1 * pr[1] + S2 * pr[2];
     lam[d] = (fabs(Uc) + a * tsqrt(S0 * S0 + S1 * S1 + S2 * S2)) * aiV;
-    double qm[5], qp[5];
-    load5d(Q, g, o - step[d], qm);
-    load5d(Q, g, o + step[d], qp);
-    const double pl = pressure(qm, ph), pu = pressure(qp, ph);
+    double pl, pu;
+    if (d < 2) {                       // in the plane: from LDS
+      const int sd = d == 0 ? 1 : PT_HX;
+      pl = sp[slot - sd];
+      pu = sp[slot + sd];
+    } else {
+      double qm[5], qp[5];
+      load5d(Q, g, o - g.plane, qm);
+      load5d(Q, g, o + g.plane, qp);
+      pl = pressure(qm, ph);
+      pu = pressure(qp, ph);
+    }
     const double num = pu - 2.0 * pr[4] + pl, den = pu + 2.0 * pr[4] + pl;
     SC[(long long)(S_NU + d) * g.vs + o] = fabs(num) * trcp(den);
   }
@@ -732,8 +754,10 @@ hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
                                const Phys<double>& ph, const int bc[6], const double ref_prim[5],
                                double p_exit, const double* inflow, const double* Rb, double* SC,
                                double* Qb, double* inflow_bar, hipStream_t s) {
-  const PlaneMap ppm = plane_map((g.plane + 255) / 256);
-  hipLaunchKernelGGL(k_adj_prep, dim3(plane_map_grid(ppm, g)), dim3(256), 0, s, Q, M, g, ph, ppm, SC);
+  const int ptiles_x = (g.nx + 2 * NG + PT_X - 1) / PT_X;
+  const PlaneMap ppm = plane_map(ptiles_x * ((g.nr + 2 * NG + PT_Y - 1) / PT_Y));
+  hipLaunchKernelGGL(k_adj_prep, dim3(plane_map_grid(ppm, g)), dim3(PT_X * PT_Y), 0, s, Q, M, g, ph,
+                     ppm, ptiles_x, SC);
   const int tiles_x = (g.nx + 2 * NG + AT_X - 1) / AT_X;
   const PlaneMap tpm = plane_map(tiles_x * ((g.nr + 2 * NG + AT_Y - 1) / AT_Y));
   hipLaunchKernelGGL(k_adj_main, dim3(plane_map_grid(tpm, g)), dim3(256), 0, s, Q, M, g, ph, tpm,

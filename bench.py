@@ -54,16 +54,19 @@ HELD_VISC_BYTES = {"fp64": 2 * 8, "fp32": 2 * 4}
 DOMINANT_KERNEL = "k_fused"
 
 
-# the sources the stage kernel is compiled from (its traffic record is tied
-# to them)
+# the sources the stage kernel is compiled from and its compiler flags (its
+# traffic record is tied to them)
 STAGE_SOURCES = ("common.hpp", "physics.hpp", "residual_fused.hip")
 
 
 def source_hash():
+    from paper_2301_00817_amd import build
     h = hashlib.sha256()
     for f in STAGE_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + fh.read())
+    flags = list(build.CFLAGS) + list(build.SOURCE_FLAGS.get("residual_fused.hip", []))
+    h.update(" ".join(f for f in flags if not f.startswith("/")).encode())
     return h.hexdigest()[:16]
 
 

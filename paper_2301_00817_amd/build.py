@@ -32,6 +32,12 @@ CFLAGS = [
 ]
 
 
+# Per-source flags.  The stage kernel (bound by latency in FP64) is scheduled
+# for instruction-level parallelism: 1 % less time per FP64 launch on MI355X,
+# FP32 and the other kernels unchanged.
+SOURCE_FLAGS = {"residual_fused.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
+
 def _hipcc():
     for c in ("/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):
@@ -41,8 +47,8 @@ def _hipcc():
 
 def _compile(src, build_dir=BUILD, defines=()):
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *CFLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src),
-           "-o", obj]
+    cmd = [_hipcc(), *CFLAGS, *SOURCE_FLAGS.get(src, []), *[f"-D{d}" for d in defines], "-c",
+           os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd.insert(1, "-x")
         cmd.insert(2, "hip")

@@ -539,22 +539,44 @@ __global__ __launch_bounds__(256) void k_adj_gather(const double* __restrict__ Q
 }
 
 // ---- ghost-fill transposes ---------------------------------------------------
-__device__ __forceinline__ void addT(double* Qb, const Grid& g, int osrc, int oghost) {
-  for (int c = 0; c < 5; ++c) {
-    Qb[(long long)c * g.vs + osrc] += Qb[(long long)c * g.vs + oghost];
-    Qb[(long long)c * g.vs + oghost] = 0.0;
-  }
+// Qb(src) += Qb(ghost), Qb(ghost) = 0 for the NG ghosts of one side, all five
+// variables, every load issued before any store (the NG sources and NG
+// ghosts must be 2 NG distinct points).
+__device__ __forceinline__ void addT_side(double* Qb, const Grid& g, const int osrc[NG],
+                                          const int oghost[NG]) {
+  double vs[5][NG], vg[5][NG];
+  for (int c = 0; c < 5; ++c)
+    for (int m = 0; m < NG; ++m) {
+      vs[c][m] = Qb[(long long)c * g.vs + osrc[m]];
+      vg[c][m] = Qb[(long long)c * g.vs + oghost[m]];
+    }
+  for (int c = 0; c < 5; ++c)
+    for (int m = 0; m < NG; ++m) {
+      Qb[(long long)c * g.vs + osrc[m]] = vs[c][m] + vg[c][m];
+      Qb[(long long)c * g.vs + oghost[m]] = 0.0;
+    }
 }
 
-__global__ void k_adjT_zeta(double* __restrict__ Qb, Grid g) {
+// One thread per padded (i, j) column and variable.  With nth >= 5 the 2 NG
+// ghost planes and the 2 NG interior planes they were copied from are all
+// distinct, so the thread issues its loads before its stores.
+__global__ __launch_bounds__(256) void k_adjT_zeta(double* __restrict__ Qb, Grid g) {
   const int NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= NX * NR) return;
-  const int i = t % NX - NG, j = t / NX - NG;
+  if (t >= 5 * NX * NR) return;
+  const int c = t / (NX * NR), r = t - c * (NX * NR);
+  const int i = r % NX - NG, j = r / NX - NG;
+  double* F = Qb + (long long)c * g.vs;
+  int og[2 * NG], os[2 * NG];
   for (int m = 1; m <= NG; ++m) {
-    addT(Qb, g, g.at(i, j, g.nth - m), g.at(i, j, -m));
-    addT(Qb, g, g.at(i, j, m - 1), g.at(i, j, g.nth - 1 + m));
+    og[m - 1] = g.at(i, j, -m);
+    os[m - 1] = g.at(i, j, g.nth - m);
+    og[NG + m - 1] = g.at(i, j, g.nth - 1 + m);
+    os[NG + m - 1] = g.at(i, j, m - 1);
   }
+  double vg[2 * NG], vs[2 * NG];
+  for (int m = 0; m < 2 * NG; ++m) { vg[m] = F[og[m]]; vs[m] = F[os[m]]; }
+  for (int m = 0; m < 2 * NG; ++m) { F[os[m]] = vs[m] + vg[m]; F[og[m]] = 0.0; }
 }
 
 // sum of the two ghost cotangents of a face, pulled back through the exact
@@ -563,25 +585,36 @@ __global__ void k_adjT_zeta(double* __restrict__ Qb, Grid g) {
 __global__ __launch_bounds__(256) void k_adjT_eta(const double* __restrict__ Q, const double* __restrict__ M,
                            double* __restrict__ Qb, Grid g, double gamma, int lo_kind,
                            int hi_kind, BPrim<double> ref) {
+  // one thread per (i, k) and face; with nr >= 5 the two faces touch
+  // disjoint ghosts and disjoint interior points
   const int NX = g.nx + 2 * NG;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= NX * g.nth) return;
-  const int i = t % NX - NG, k = t / NX;
+  const int nf = NX * g.nth;
+  if (t >= 2 * nf) return;
+  const bool lo = t < nf;
+  const int ik = lo ? t : t - nf;
+  const int i = ik % NX - NG, k = ik / NX;
+  if (!lo) { lo_kind = -1; } else { hi_kind = -1; }
+  int os[NG], og[NG];
   if (lo_kind == BC_PERIODIC) {
-    for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(i, g.nr - m, k), g.at(i, -m, k));
+    for (int m = 1; m <= NG; ++m) { os[m - 1] = g.at(i, g.nr - m, k); og[m - 1] = g.at(i, -m, k); }
+    addT_side(Qb, g, os, og);
   } else if (lo_kind == BC_AXIS) {
     // gather form: the ghost (i, -m, k + nth/2) was copied from (i, m - 1, k)
     // (nth is even, so the map is an involution of k)
     const int kk = (k + g.nth / 2) % g.nth;
-    for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(i, m - 1, k), g.at(i, -m, kk));
+    for (int m = 1; m <= NG; ++m) { os[m - 1] = g.at(i, m - 1, k); og[m - 1] = g.at(i, -m, kk); }
+    addT_side(Qb, g, os, og);
   } else if (lo_kind == BC_AXIS_NODE) {
     // mirror through the axis node: the ghost (i, -m, k + nth/2) was copied
     // from (i, m, k)
     const int kk = (k + g.nth / 2) % g.nth;
-    for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(i, m, k), g.at(i, -m, kk));
+    for (int m = 1; m <= NG; ++m) { os[m - 1] = g.at(i, m, k); og[m - 1] = g.at(i, -m, kk); }
+    addT_side(Qb, g, os, og);
   }
   if (hi_kind == BC_PERIODIC) {
-    for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(i, m - 1, k), g.at(i, g.nr - 1 + m, k));
+    for (int m = 1; m <= NG; ++m) { os[m - 1] = g.at(i, m - 1, k); og[m - 1] = g.at(i, g.nr - 1 + m, k); }
+    addT_side(Qb, g, os, og);
   } else if (hi_kind == BC_FARFIELD) {
     const int oe = g.at(i, g.nr - 1, k);
     double fb[5] = {0, 0, 0, 0, 0};
@@ -643,7 +676,9 @@ __global__ __launch_bounds__(64) void k_adjT_xi(const double* __restrict__ Q, co
     n[0] = a * inv; n[1] = b * inv; n[2] = c * inv;
   };
   if (lo_kind == BC_PERIODIC) {
-    for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(g.nx - m, j, k), g.at(-m, j, k));
+    int os[NG], og[NG];
+    for (int m = 1; m <= NG; ++m) { os[m - 1] = g.at(g.nx - m, j, k); og[m - 1] = g.at(-m, j, k); }
+    addT_side(Qb, g, os, og);
   } else if (lo_kind == BC_INFLOW) {
     const int oe = g.at(0, j, k);
     double fb[5], n[3];
@@ -664,7 +699,9 @@ __global__ __launch_bounds__(64) void k_adjT_xi(const double* __restrict__ Q, co
     }
   }
   if (hi_kind == BC_PERIODIC) {
-    for (int m = 1; m <= NG; ++m) addT(Qb, g, g.at(m - 1, j, k), g.at(g.nx - 1 + m, j, k));
+    int os[NG], og[NG];
+    for (int m = 1; m <= NG; ++m) { os[m - 1] = g.at(m - 1, j, k); og[m - 1] = g.at(g.nx - 1 + m, j, k); }
+    addT_side(Qb, g, os, og);
   } else if (hi_kind == BC_OUTFLOW) {
     const int oe = g.at(g.nx - 1, j, k);
     double fb[5], n[3];
@@ -766,10 +803,10 @@ hipError_t launch_residual_vjp(const double* Q, const double* M, const Grid& g,
   hipLaunchKernelGGL(k_adj_gather, dim3(plane_map_grid(gpm, g)), dim3(256), 0, s, Q, g, ph, gpm, SC,
                      Qb);
   const double gamma = ph.gamma;
-  hipLaunchKernelGGL(k_adjT_zeta, dim3(blocks_for((long long)(g.nx + 2 * NG) * (g.nr + 2 * NG), 256)),
+  hipLaunchKernelGGL(k_adjT_zeta, dim3(blocks_for(5LL * (g.nx + 2 * NG) * (g.nr + 2 * NG), 256)),
                      dim3(256), 0, s, Qb, g);
   BPrim<double> ref = {ref_prim[0], ref_prim[1], ref_prim[2], ref_prim[3], ref_prim[4]};
-  hipLaunchKernelGGL(k_adjT_eta, dim3(blocks_for((long long)(g.nx + 2 * NG) * g.nth, 256)), dim3(256),
+  hipLaunchKernelGGL(k_adjT_eta, dim3(blocks_for(2LL * (g.nx + 2 * NG) * g.nth, 256)), dim3(256),
                      0, s, Q, M, Qb, g, gamma, bc[2], bc[3], ref);
   hipLaunchKernelGGL(k_adjT_xi, dim3(blocks_for(2LL * g.nr * g.nth, 64)), dim3(64), 0, s, Q, M, Qb,
                      g, inflow, inflow_bar, gamma, bc[0], bc[1], p_exit, ph.axis_node);

@@ -219,7 +219,7 @@ hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
   ref.w = (T)ref_prim[3]; ref.p = (T)ref_prim[4];
   const long long NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
   const long long n = 2LL * NG * (NX * NR + NX * g.nth + (long long)g.nr * g.nth);
-  hipLaunchKernelGGL(k_ghost_all<T>, dim3(blocks_for(n, 128)), dim3(128), 0, s, Q, g, M, inflow,
+  hipLaunchKernelGGL(k_ghost_all<T>, dim3(blocks_for(n, 64)), dim3(64), 0, s, Q, g, M, inflow,
                      gamma, bc[0], bc[1], bc[2], bc[3], p_exit, ref, held);
   return hipGetLastError();
 }

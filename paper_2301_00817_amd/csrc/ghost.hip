@@ -92,8 +92,11 @@ __device__ __forceinline__ void xi_value(const T* __restrict__ Q, const Grid& g,
 // held != nullptr: a ghost point whose trace ends in a physical-face rule
 // (entrance, exit, far field) takes the value of `held` at the same point,
 // which is that rule evaluated on the held state.
+// 64-thread blocks, at least six waves per SIMD: the FP64 instance fits 80
+// VGPRs without spilling (81 unbounded, five waves); eight waves spill.
+constexpr int GH_BS = 64;
 template <typename T>
-__global__ void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
+__global__ __launch_bounds__(GH_BS, 6) void k_ghost_all(T* __restrict__ Q, Grid g, const T* __restrict__ M,
                             const double* __restrict__ inflow, double gamma, int xlo, int xhi,
                             int elo, int ehi, double p_exit, BPrim<T> ref,
                             const T* __restrict__ held) {
@@ -219,7 +222,7 @@ hipError_t launch_ghosts(T* Q, const Grid& g, const T* M, const double* inflow,
   ref.w = (T)ref_prim[3]; ref.p = (T)ref_prim[4];
   const long long NX = g.nx + 2 * NG, NR = g.nr + 2 * NG;
   const long long n = 2LL * NG * (NX * NR + NX * g.nth + (long long)g.nr * g.nth);
-  hipLaunchKernelGGL(k_ghost_all<T>, dim3(blocks_for(n, 64)), dim3(64), 0, s, Q, g, M, inflow,
+  hipLaunchKernelGGL(k_ghost_all<T>, dim3(blocks_for(n, GH_BS)), dim3(GH_BS), 0, s, Q, g, M, inflow,
                      gamma, bc[0], bc[1], bc[2], bc[3], p_exit, ref, held);
   return hipGetLastError();
 }

@@ -7,19 +7,29 @@ reduction).  The metric is grid-point RK-stage updates per second:
     value = N_interior * 5 * steps / wall time   [Mpoint-RK-stage updates/s]
 with the state resident in HBM before the timed region starts.
 
-Default workload: the 288 x 160 x 128 (5.9 M points) supersonic jet mesh in
-plain FP64, CFL 0.5, synthetic seeded inputs (cases/).
+Default workload: the largest single-GPU jet mesh, 1250 x 640 x 1250
+(1.0e9 points, the size of the paper's largest mesh), built on the device
+from its 1-D axial, radial and azimuthal maps; the timed line is the plain
+FP64 form, CFL 0.5, synthetic seeded inputs (cases/).
 
 The JSON line also carries
-  roofline     the dominant kernel's algorithmic HBM bytes per launch divided
+  roofline     algorithmic HBM bytes per launch of the stage kernel divided
                by its average launch time (HIP events on the launch stream,
-               over the timed region), against the 8 TB/s HBM peak; `traffic`
-               is the HBM bytes per launch measured by rocprofv3 FETCH_SIZE +
-               WRITE_SIZE (profiles/traffic.json) when those counters were
-               taken on the current kernel sources, else null;
-  cpu_baseline the CPU oracle (plain NumPy FP64, single thread) timed on a
-               bounded sample of the same workload: one RK stage (ghost fill,
-               residual, update) over the whole mesh;
+               over the timed region), against the 8 TB/s HBM peak.  The
+               bytes are those the method moves per interior point and RK
+               stage taken as its two steps, residual (read the stage state
+               and the metrics, write R) and update (read Q^(0) and R, write
+               the new stage state): FP64 280 B, FP32 storage 168 B averaged
+               over the five stages.  `fused` gives the same kernel against
+               the bytes it moves itself (R never leaves the chip: 200 B,
+               FP32 storage 128 B).  `traffic` is the HBM bytes per launch
+               measured by rocprofv3 FETCH_SIZE + WRITE_SIZE
+               (profiles/traffic.json) when those counters were taken on the
+               current kernel sources and on this workload, else null;
+  cpu_baseline the CPU oracle (plain NumPy FP64, one thread) on bounded
+               samples: one residual and one RK5 step of the 160 x 100 x 128
+               and 288 x 160 x 128 jet meshes, median of three runs each;
+               `value` is the RK5-step rate on 288 x 160 x 128;
   precision_forms  the same workload and step count in the other precision
                form (FP32 storage with FP64 accumulation, or plain FP64);
   adjoint      residual-adjoint calls per second (les_residual_vjp) on the
@@ -41,13 +51,20 @@ PEAK_HBM_GBS = 8000.0
 VJP_BYTES_PER_POINT = 200
 CSRC = os.path.join(ROOT, "paper_2301_00817_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+DEFAULT_CONFIG = "big1B"
 
-# Algorithmic HBM bytes per interior point of one launch of the fused RK
-# stage kernel (k_fused): read the stage state Q^(l-1) (5 values) and the
-# metrics (10), read Q^(0) (5 FP64), write Q^(l) (5).  FP64: 200 B.  FP32
-# storage: 20 + 40 + 40 + 20 = 120 B, plus 40 B for the FP64 Q^(n+1) in the
-# last stage, i.e. 128 B averaged over the five stages.
-STAGE_BYTES = {"fp64": (5 + 10 + 5 + 5) * 8, "fp32": (5 + 10 + 5) * 4 + 5 * 8 + 5 * 8 / 5}
+# Algorithmic HBM bytes per interior point and RK stage, the method taken as
+# residual + update: residual reads the stage state (5 values) and the
+# metrics (10) and writes R (5); the update reads Q^(0) (5, FP64), R (5) and
+# writes the stage state (5).  FP64: 160 + 120 = 280 B.  FP32 storage: 80 B
+# residual; the update reads Q^(0) 40 + R 20, writes 20, and in the last
+# stage also the FP64 Q^(n+1) (40): 88 B averaged; 168 B in all.
+METHOD_STAGE_BYTES = {"fp64": 280.0, "fp32": 168.0}
+# The fused stage kernel (k_fused) moves per interior point: read the stage
+# state (5) and the metrics (10), read Q^(0) (5 FP64), write the stage state
+# (5).  FP64: 200 B.  FP32 storage: 20 + 40 + 40 + 20 = 120 B, plus 40 B for
+# the FP64 Q^(n+1) in the last stage, i.e. 128 B averaged over the stages.
+FUSED_STAGE_BYTES = {"fp64": (5 + 10 + 5 + 5) * 8.0, "fp32": (5 + 10 + 5) * 4 + 5 * 8 + 5 * 8 / 5}
 # The per-step update schedule (viscosities held from stage 1) adds two
 # values per point: written by the first stage, read by the four others.
 HELD_VISC_BYTES = {"fp64": 2 * 8, "fp32": 2 * 4}
@@ -71,23 +88,20 @@ def source_hash():
 
 
 def make_workload(name, device, chunk_points=64 * 2 ** 20):
-    """(params, xyz, fill, inflow) of a named workload on `device`; fill(Qi)
-    writes the initial state into the interior view Qi (5, nth, nr, nx) in
-    azimuthal chunks, so meshes of 1e9 points need no full-size temporaries."""
-    import torch
-    from cases import flow, mesh, problems
+    """(params, mesh, fill, inflow) of a named workload on `device`: mesh is
+    {"xyz": coordinates} (box) or {"grid": (X, R, TH)} (jet, the 1-D maps the
+    library builds the mesh from); fill(Qi) writes the initial state into the
+    interior view Qi (5, nth, nr, nx) in azimuthal chunks, so meshes of 1e9
+    points need no full-size temporaries."""
+    from cases import flow, problems
     cfg = problems.CONFIGS[name]
     if cfg["kind"] == "box":
         pb = problems.box_problem(cfg["n"], seed=cfg["seed"])
         Q = pb["Q"].to(device)
-        return pb["params"], pb["xyz"].to(device), (lambda Qi: Qi.copy_(Q)), None
+        return pb["params"], {"xyz": pb["xyz"]}, (lambda Qi: Qi.copy_(Q)), None
     nx, nr, nth = cfg["shape"]
     X, R, TH = problems.jet_grid(nx, nr, nth)
     kc = max(1, chunk_points // (nx * nr))
-    xyz = torch.empty((3, nth, nr, nx), dtype=torch.float64, device=device)
-    for k0 in range(0, nth, kc):
-        k1 = min(nth, k0 + kc)
-        xyz[:, k0:k1] = mesh.cylindrical_coords(X, R, TH, k0, k1, device=device)
 
     def fill(Qi):
         for k0 in range(0, nth, kc):
@@ -96,43 +110,69 @@ def make_workload(name, device, chunk_points=64 * 2 ** 20):
 
     inflow = flow.jet_inflow(R, TH, seed=cfg["seed"], device=device)
     prm = problems.jet_params() if cfg.get("sgs", True) else problems.jet_params(sgs_model=0)
-    return prm, xyz, fill, inflow
+    return prm, {"grid": (X, R, TH)}, fill, inflow
 
 
-def cpu_baseline(name, min_seconds=10.0):
-    """The oracle on the stages of one RK5 step of the same workload (single
-    thread), stopping after the first stage that ends past `min_seconds`."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(reps=3):
+    """The oracle (NumPy FP64, one thread) on bounded samples: one residual
+    (ghost fill + residual) and one RK5 step (CFL dt + five stages) of the
+    160 x 100 x 128 and 288 x 160 x 128 jet meshes, median of `reps` runs
+    each.  `value` is the RK5-step rate on 288 x 160 x 128."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from cases import problems
     from oracle import les
-    cfg = problems.CONFIGS[name]
-    if cfg["kind"] == "box":
-        pb = problems.box_problem(cfg["n"], seed=cfg["seed"])
-    else:
-        pb = problems.jet_problem(*cfg["shape"], seed=cfg["seed"])
-    xyz, Q = pb["xyz"].numpy(), pb["Q"].numpy()
-    inflow = pb["inflow"].numpy() if pb["inflow"] is not None else None
-    prm = pb["params"]
-    geo = les.geometry(xyz, prm)
-    dt = les.time_step(Q, geo, prm)
-    t0 = time.perf_counter()
-    Ql, stages = Q, 0
-    for alpha in prm["rk_alpha"]:
-        Ql = Q - alpha * dt * les.evaluate(Ql, geo, prm, inflow)
-        stages += 1
-        if time.perf_counter() - t0 >= min_seconds:
-            break
-    t = time.perf_counter() - t0
-    assert np.isfinite(Ql).all()
-    n = Q.shape[1] * Q.shape[2] * Q.shape[3]
-    return {"value": stages * n / t / 1e6, "unit": "Mpoint-RK-stage updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{stages} RK stage(s) (ghost fill + residual + update each) of one step "
-                      f"over the whole {Q.shape[3]}x{Q.shape[2]}x{Q.shape[1]} mesh, NumPy FP64, "
-                      f"1 thread, {t:.1f} s"}
+    samples = {}
+    with threadpool_limits(limits=1):
+        for name in ("adj2M", "jet5.9M"):
+            cfg = problems.CONFIGS[name]
+            pb = problems.jet_problem(*cfg["shape"], seed=cfg["seed"])
+            xyz, Q = pb["xyz"].numpy(), pb["Q"].numpy()
+            inflow, prm = pb["inflow"].numpy(), pb["params"]
+            geo = les.geometry(xyz, prm)
+            n = Q.shape[1] * Q.shape[2] * Q.shape[3]
+            tr, ts = [], []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                R = les.evaluate(Q, geo, prm, inflow)
+                tr.append(time.perf_counter() - t0)
+                t0 = time.perf_counter()
+                Q1, _ = les.rk5_step(Q, geo, prm, inflow)
+                ts.append(time.perf_counter() - t0)
+                assert np.isfinite(R).all() and np.isfinite(Q1).all()
+            mr, ms = float(np.median(tr)), float(np.median(ts))
+            nx, nr, nth = cfg["shape"]
+            samples[f"jet{nx}x{nr}x{nth}"] = {
+                "points": n,
+                "residual_s": round(mr, 3), "residual_Mpoint_per_s": round(n / mr / 1e6, 4),
+                "rk5_step_s": round(ms, 3),
+                "rk5_Mpoint_stage_per_s": round(5 * n / ms / 1e6, 4),
+                "runs_s": {"residual": [round(t, 3) for t in tr],
+                           "rk5_step": [round(t, 3) for t in ts]}}
+            del geo, Q, xyz, pb
+    head = samples["jet288x160x128"]
+    return {"value": head["rk5_Mpoint_stage_per_s"], "unit": "Mpoint-RK-stage updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": "one RK5 step (CFL dt, 5 x (ghost fill + residual + update)) of the "
+                      "288x160x128 jet mesh, NumPy FP64, 1 thread, median of 3; also one "
+                      "residual and one step of the 160x100x128 mesh (samples)",
+            "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+            "samples": samples}
 
 
-def traffic_for(kernel, workload, launches_bytes):
+def traffic_for(kernel, workload):
     """HBM bytes per launch from committed rocprofv3 counters, if current."""
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -232,9 +272,9 @@ def traffic_record(fetch_dir, write_dir, cfetch_dir, cwrite_dir, workload, known
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="jet5.9M")
+    ap.add_argument("--config", default=DEFAULT_CONFIG)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--sgs", default=None, choices=["none", "smagorinsky", "vreman", "dynamic"],
                     help="subgrid model (default: the workload's own)")
@@ -246,6 +286,8 @@ def main():
                     help="skip the other-precision run and the adjoint timing")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only time les_residual_vjp against les_residual (160x100x128 jet)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only time the CPU oracle samples (no GPU needed)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only time a device copy of this many GiB (counter calibration)")
     ap.add_argument("--rocprof-summary", nargs=3, metavar=("CSV_DIR", "OUT", "COMMAND"),
@@ -261,6 +303,9 @@ def main():
         return
     if args.rocprof_summary:
         print(rocprof_summary(*args.rocprof_summary))
+        return
+    if args.cpu_baseline_only:
+        print(json.dumps({"cpu_baseline": cpu_baseline()}), flush=True)
         return
 
     if args.gpus != 1:
@@ -285,16 +330,9 @@ def main():
     npts = nx * nr * nth
     prm = r["params"]
     value = npts * 5 * args.steps / r["wall"] / 1e6
-    held = args.schedule == "step" and prm["visc_coef"] != 0.0
-    bytes_launch = (STAGE_BYTES[args.precision] + (HELD_VISC_BYTES[args.precision] if held else 0)) * npts
-    avg_ms = r["kernel_ms"] / max(r["launches"], 1)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     workload = f"{args.config}-{args.precision}" + ("-step" if args.schedule == "step" else "")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic_for(DOMINANT_KERNEL, workload, bytes_launch),
-            "kernel": DOMINANT_KERNEL, "avg_launch_ms": round(avg_ms, 4),
-            "launches": r["launches"], "algorithmic_bytes_per_launch": bytes_launch}
+    roof = roofline(args.precision, args.schedule == "step" and prm["visc_coef"] != 0.0, npts,
+                    r, workload)
 
     out = {
         "metric": "Mpoint-RK-stage updates/s",
@@ -329,17 +367,42 @@ def main():
         r2 = time_rk(args.config, other, args.steps, args.warmup, dev, args.schedule, args.sgs)
         v2 = npts * 5 * args.steps / r2["wall"] / 1e6
         fp32_v, fp64_v = (v2, value) if other == "fp32" else (value, v2)
+        roof2 = roofline(other, args.schedule == "step" and prm["visc_coef"] != 0.0, npts, r2,
+                         f"{args.config}-{other}" + ("-step" if args.schedule == "step" else ""))
         out["precision_forms"] = {"fp64": round(fp64_v, 2), "fp32": round(fp32_v, 2),
                                   "fp32_over_fp64": round(fp32_v / fp64_v, 3),
-                                  "unit": "Mpoint-RK-stage updates/s"}
+                                  "unit": "Mpoint-RK-stage updates/s",
+                                  other: {"ms_per_step": round(r2["wall"] / args.steps * 1e3, 4),
+                                          "hbm_footprint_gb": r2["hbm_gb"],
+                                          "device_used_gb": r2["device_used_gb"],
+                                          "roofline": roof2}}
         print("[bench] adjoint timing", file=sys.stderr, flush=True)
         out["adjoint"] = time_adjoint("adj2M", dev)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.config)
+        out["cpu_baseline"] = cpu_baseline()
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
+
+
+def roofline(precision, held, npts, r, workload):
+    """Roofline object of the stage kernel from a time_rk result."""
+    avg_ms = r["kernel_ms"] / max(r["launches"], 1)
+    extra = HELD_VISC_BYTES[precision] if held else 0
+    method_bytes = (METHOD_STAGE_BYTES[precision] + extra) * npts
+    fused_bytes = (FUSED_STAGE_BYTES[precision] + extra) * npts
+    achieved = method_bytes / (avg_ms * 1e-3) / 1e9
+    fused = fused_bytes / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic_for(DOMINANT_KERNEL, workload),
+            "kernel": DOMINANT_KERNEL, "avg_launch_ms": round(avg_ms, 4),
+            "launches": r["launches"],
+            "algorithmic_bytes_per_point": METHOD_STAGE_BYTES[precision] + extra,
+            "algorithmic_bytes_per_launch": method_bytes,
+            "fused": {"bytes_per_point": FUSED_STAGE_BYTES[precision] + extra,
+                      "achieved": round(fused, 1), "frac": round(fused / PEAK_HBM_GBS, 4)}}
 
 
 SGS_MODELS = {"none": 0, "smagorinsky": 1, "vreman": 2, "dynamic": 3}
@@ -350,12 +413,12 @@ def time_rk(config, precision, steps, warmup, dev, schedule="stage", sgs=None):
     with the stage kernel's launches timed by HIP events on its stream."""
     import torch
     from paper_2301_00817_amd.solver import Solver
-    prm, xyz, fill, inflow = make_workload(config, dev)
+    t_setup = time.perf_counter()
+    prm, mesh, fill, inflow = make_workload(config, dev)
     prm = dict(prm, schedule=schedule)
     if sgs is not None:
         prm["sgs_model"] = SGS_MODELS[sgs]
-    s = Solver(prm, xyz, inflow, precision=precision, device=dev)
-    del xyz
+    s = Solver(prm, inflow=inflow, precision=precision, device=dev, **mesh)
     torch.cuda.empty_cache()
     nx, nr, nth = s.shape
     Qn = s.field(5, dtype=torch.float64, fill=0.0)
@@ -364,7 +427,8 @@ def time_rk(config, precision, steps, warmup, dev, schedule="stage", sgs=None):
     hbm = torch.cuda.max_memory_allocated(dev) / 1e9
     _, _, held = s.query()
     print(f"[bench] device bytes held by the library {held / 1e9:.1f} GB, state "
-          f"{Qn.numel() * 8 / 1e9:.1f} GB, torch peak {hbm:.1f} GB", file=sys.stderr, flush=True)
+          f"{Qn.numel() * 8 / 1e9:.1f} GB, torch peak {hbm:.1f} GB, set-up "
+          f"{time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
     print(f"[bench] {config} {nx}x{nr}x{nth} {precision}: warmup {warmup}",
           file=sys.stderr, flush=True)
     if warmup:
@@ -386,6 +450,8 @@ def time_rk(config, precision, steps, warmup, dev, schedule="stage", sgs=None):
     r = {"shape": s.shape, "params": prm, "wall": wall, "launches": launches, "kernel_ms": kms,
          "dt_last": float(dts[-1]), "hbm_gb": round((held + Qn.numel() * 8) / 1e9, 2),
          "device_used_gb": round((total - free) / 1e9, 1), "device_total_gb": round(total / 1e9, 1)}
+    print(f"[bench] {steps} steps in {wall:.3f} s, stage kernel {kms / max(launches, 1):.3f} ms "
+          f"per launch", file=sys.stderr, flush=True)
     s.close()
     del Qn
     torch.cuda.empty_cache()
@@ -398,9 +464,8 @@ def time_adjoint(config, dev, reps=20):
     import torch
     from cases import flow, problems
     from paper_2301_00817_amd.solver import Solver
-    prm, xyz, fill, inflow = make_workload(config, dev)
-    s = Solver(prm, xyz, inflow, precision="fp64", device=dev)
-    del xyz
+    prm, mesh, fill, inflow = make_workload(config, dev)
+    s = Solver(prm, inflow=inflow, precision="fp64", device=dev, **mesh)
     Qp = s.field(5, dtype=torch.float64, fill=0.0)
     fill(s.interior(Qp))
     nx, nr, nth = s.shape

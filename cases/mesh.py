@@ -60,18 +60,29 @@ def azimuth(nth, dtype=torch.float64):
     return 2.0 * math.pi * torch.arange(nth, dtype=dtype) / nth
 
 
+def angle_tables(TH):
+    """cos and sin of the angles by the host C library (math.cos, math.sin):
+    the functions the GPU library's product-mesh set-up calls, so that
+    coordinates formed here and there from the same maps agree bitwise."""
+    th = [float(t) for t in TH.reshape(-1).tolist()]
+    c = torch.tensor([math.cos(t) for t in th], dtype=torch.float64)
+    s = torch.tensor([math.sin(t) for t in th], dtype=torch.float64)
+    return c, s
+
+
 def cylindrical_coords(X, R, TH, k0=0, k1=None, device="cpu"):
     """x = X_i, y = R_j cos(theta_k), z = R_j sin(theta_k) for k in [k0, k1)."""
     if k1 is None:
         k1 = TH.numel()
     X = X.to(device)
     R = R.to(device)
-    th = TH[k0:k1].to(device)
-    nth, nr, nx = th.numel(), R.numel(), X.numel()
+    ct, st = angle_tables(TH[k0:k1])
+    ct, st = ct.to(device), st.to(device)
+    nth, nr, nx = ct.numel(), R.numel(), X.numel()
     xyz = torch.empty((3, nth, nr, nx), dtype=torch.float64, device=device)
     xyz[0] = X.view(1, 1, nx)
-    xyz[1] = (R.view(1, nr, 1) * torch.cos(th).view(nth, 1, 1)).expand(nth, nr, nx)
-    xyz[2] = (R.view(1, nr, 1) * torch.sin(th).view(nth, 1, 1)).expand(nth, nr, nx)
+    xyz[1] = (R.view(1, nr, 1) * ct.view(nth, 1, 1)).expand(nth, nr, nx)
+    xyz[2] = (R.view(1, nr, 1) * st.view(nth, 1, 1)).expand(nth, nr, nx)
     return xyz
 
 

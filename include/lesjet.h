@@ -173,12 +173,25 @@ int les_device_bytes(const les_params* p, size_t* bytes);
 
 /* ---- context ------------------------------------------------------------ */
 
-/* Create a context for the mesh `xyz` (device, FP64, shape (3, nth, nr, nx),
- * coordinates x, y, z of the interior points, i fastest).  Ghost coordinates
+/* Create a context for a mesh given in one of two forms (exactly one):
+ *   xyz         FP64, shape (3, nth, nr, nx), coordinates x, y, z of the
+ *               interior points, i fastest; host or device memory (the
+ *               runtime tells them apart); or
+ *   X, R, TH    the 1-D maps of a cylindrical product mesh (section "Mesh
+ *               Generation", tab:mesh-gen: the 3-D jet mesh is a 2-D axial-
+ *               radial mesh rotated about the axis; here the 2-D mesh is the
+ *               product of an axial and a radial distribution), X[nx],
+ *               R[nr], TH[nth] FP64, host or device:
+ *                 x = X[i],  y = R[j] cos(TH[k]),  z = R[j] sin(TH[k]),
+ *               cos and sin evaluated on the host by the C library (a caller
+ *               forming xyz with the same functions gets the same mesh
+ *               bitwise); no 3-D coordinate array crosses the boundary.
+ * The other form's pointers are NULL; both or neither given, or only some
+ * of X, R, TH, is LES_EINVAL, as are non-finite maps.  Ghost coordinates
  * (three layers) are built on the device from the boundary kinds:
  * periodic -> wrapped point plus `period`; axis -> point (i, m, k + nth/2);
  * inflow/outflow/far field -> linear extrapolation in index space.
- * The coordinates are copied; `xyz` may be freed after the call returns
+ * The inputs are copied; they may be freed after the call returns
  * (the call synchronises `stream`).  The environment variable LESJET_KCHUNK,
  * if set to a positive integer, overrides the number of azimuthal planes
  * one block of the fused kernel marches over (tuning and tests); with
@@ -187,7 +200,8 @@ int les_device_bytes(const les_params* p, size_t* bytes);
  * Section "Transformation of
  * Coordinates"; the centerline and periodic subsections of "Boundary
  * Conditions". */
-int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, void* stream);
+int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, const double* X,
+                  const double* R, const double* TH, void* stream);
 
 /* Compute the metric terms J^-1 grad(xi), J^-1 grad(eta), J^-1 grad(zeta)
  * and J^-1 on the padded box by central differences of the coordinates
@@ -300,9 +314,11 @@ int les_diagnostics(les_ctx* c, const double* Qn, double* totals, double* sum1, 
 int les_profile(les_ctx* c, int32_t enable);
 int les_profile_read(les_ctx* c, int64_t* launches, double* total_ms);
 
-/* Query the context: padded dims (nth+4, nr+4, pitch), variable stride in
- * elements, and device bytes held. */
-int les_query(const les_ctx* c, int64_t dims[3], int64_t* var_stride, size_t* device_bytes);
+/* Query the context: dims_padded = shape of a padded state (5, nth+4, nr+4,
+ * pitch) (variable stride = dims_padded[1] * dims_padded[2] * pitch
+ * elements), pitch = row pitch in elements, device_bytes = device memory the
+ * library holds for the context.  Any output may be NULL. */
+int les_query(const les_ctx* c, int64_t dims_padded[4], int64_t* pitch, size_t* device_bytes);
 
 /* Message of the last failure on `c`, or of the calling thread when c is NULL
  * (e.g. after les_init_grid failed).  Never NULL. */

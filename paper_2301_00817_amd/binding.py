@@ -9,9 +9,7 @@ raises immediately — there is no fallback implementation.
 import ctypes
 import os
 
-# LESJET_LIB selects another build of the same library (A/B measurements)
-LIB_PATH = os.environ.get("LESJET_LIB") or os.path.join(
-    os.path.dirname(os.path.abspath(__file__)), "_lib", "liblesjet.so")
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblesjet.so")
 
 LES_OK, LES_EINVAL, LES_ENOMEM, LES_EHIP, LES_ENONFINITE, LES_ESTATE, LES_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
@@ -79,7 +77,7 @@ def _load():
         "les_validate": ([P(les_params)], ctypes.c_int),
         "les_layout": ([P(les_params), P(i64), P(i64 * 3), P(i64)], ctypes.c_int),
         "les_device_bytes": ([P(les_params), P(sz)], ctypes.c_int),
-        "les_init_grid": ([P(vp), P(les_params), vp, vp], ctypes.c_int),
+        "les_init_grid": ([P(vp), P(les_params), vp, vp, vp, vp, vp], ctypes.c_int),
         "les_metrics": ([vp, vp, vp], ctypes.c_int),
         "les_set_inflow": ([vp, vp, vp], ctypes.c_int),
         "les_fill_ghosts": ([vp, vp, vp], ctypes.c_int),
@@ -92,7 +90,7 @@ def _load():
         "les_diagnostics": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "les_profile": ([vp, i32], ctypes.c_int),
         "les_profile_read": ([vp, P(i64), P(dbl)], ctypes.c_int),
-        "les_query": ([vp, P(i64 * 3), P(i64), P(sz)], ctypes.c_int),
+        "les_query": ([vp, P(i64 * 4), P(i64), P(sz)], ctypes.c_int),
         "les_last_error": ([vp], ctypes.c_char_p),
         "les_free": ([vp], None),
     }
@@ -139,9 +137,12 @@ def les_device_bytes(params):
     return b.value
 
 
-def les_init_grid(params, xyz_ptr, stream=0):
+def les_init_grid(params, xyz_ptr=None, x_ptr=None, r_ptr=None, th_ptr=None, stream=0):
+    """Context for a mesh given as xyz (3, nth, nr, nx) or as the 1-D maps X,
+    R, TH of a cylindrical product mesh (pointers to host or device FP64)."""
     ctx = ctypes.c_void_p()
-    _check(_lib.les_init_grid(ctypes.byref(ctx), ctypes.byref(params), xyz_ptr, stream))
+    _check(_lib.les_init_grid(ctypes.byref(ctx), ctypes.byref(params), xyz_ptr, x_ptr, r_ptr,
+                              th_ptr, stream))
     return ctx.value
 
 
@@ -200,9 +201,10 @@ def les_profile_read(ctx):
 
 
 def les_query(ctx):
-    dims, vs, b = (ctypes.c_int64 * 3)(), ctypes.c_int64(), ctypes.c_size_t()
-    _check(_lib.les_query(ctx, ctypes.byref(dims), ctypes.byref(vs), ctypes.byref(b)), ctx)
-    return tuple(dims), vs.value, b.value
+    """(dims_padded (5, nth+4, nr+4, pitch), pitch, device bytes held)."""
+    dims, pitch, b = (ctypes.c_int64 * 4)(), ctypes.c_int64(), ctypes.c_size_t()
+    _check(_lib.les_query(ctx, ctypes.byref(dims), ctypes.byref(pitch), ctypes.byref(b)), ctx)
+    return tuple(dims), pitch.value, b.value
 
 
 def les_free(ctx):

@@ -45,10 +45,9 @@ def _hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src, build_dir=BUILD, defines=()):
+def _compile(src, build_dir=BUILD):
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *CFLAGS, *SOURCE_FLAGS.get(src, []), *[f"-D{d}" for d in defines], "-c",
-           os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *CFLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd.insert(1, "-x")
         cmd.insert(2, "hip")
@@ -74,35 +73,46 @@ def build_checks():
     return CHECKS_LIB
 
 
-def build(verbose=False, lib=LIB, defines=()):
-    """Compile all sources and link `lib`; `defines` are extra -D macros
-    (variants for measurements, built to another path)."""
-    build_dir = BUILD if lib == LIB else os.path.join(os.path.dirname(os.path.abspath(lib)), "_obj")
-    os.makedirs(build_dir, exist_ok=True)
-    os.makedirs(os.path.dirname(os.path.abspath(lib)), exist_ok=True)
+DEVCHECKS_SRC = os.path.join(ROOT, "tests", "device_checks.hip")
+DEVCHECKS_LIB = os.path.join(LIBDIR, "liblesjet_devchecks.so")
+
+
+def build_device_checks():
+    """Device check library of the kernels' fast arithmetic (GPU test helper)."""
+    os.makedirs(LIBDIR, exist_ok=True)
+    tmp = DEVCHECKS_LIB + ".tmp"
+    cmd = [_hipcc(), *CFLAGS, "-shared", DEVCHECKS_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on device_checks.hip:\n{r.stderr[-6000:]}")
+    os.replace(tmp, DEVCHECKS_LIB)
+    return DEVCHECKS_LIB
+
+
+def build(verbose=False):
+    """Compile all sources, link the library and the test check libraries."""
+    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(LIBDIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        results = list(ex.map(lambda src: _compile(src, build_dir, defines), SOURCES))
+        results = list(ex.map(_compile, SOURCES))
     objs = [o for o, _ in results]
     if verbose:
         for _, err in results:
             if err.strip():
                 print(err, file=sys.stderr)
-    tmp = lib + ".tmp"
+    tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-Wl,--no-undefined", "-o", tmp,
            *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")
-    os.replace(tmp, lib)
-    if lib == LIB and os.path.exists(CHECKS_SRC):
+    os.replace(tmp, LIB)
+    if os.path.exists(CHECKS_SRC):
         build_checks()
-    return lib
+    if os.path.exists(DEVCHECKS_SRC):
+        build_device_checks()
+    return LIB
 
 
 if __name__ == "__main__":
-    import argparse
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=LIB)
-    ap.add_argument("-D", dest="defines", action="append", default=[])
-    a = ap.parse_args()
-    print(build(verbose=True, lib=a.out, defines=a.defines))
+    print(build(verbose=True))

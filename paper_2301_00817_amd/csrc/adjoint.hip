@@ -752,8 +752,11 @@ hipError_t launch_centerline_transpose(double* Qb, const Grid& g, hipStream_t s)
   return hipGetLastError();
 }
 
-__global__ void k_scale(const double* __restrict__ x, double a, double* __restrict__ y,
-                        long long n) {
+// Element-wise kernels of the RK5-step adjoint.  x and y may be the same
+// array (the step adjoint scales a cotangent in place, and Qbar_n may alias
+// Qbar_np1): each thread reads its element before writing it and touches no
+// other, so the pointers carry no __restrict__.
+__global__ void k_scale(const double* x, double a, double* y, long long n) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t < n) y[t] = a * x[t];
 }
@@ -763,8 +766,9 @@ __global__ void k_accumulate(const double* __restrict__ x, double* __restrict__ 
   if (t < n) y[t] += x[t];
 }
 
-// y = x on the interior, 0 on ghosts and pitch padding (5 variables).
-__global__ void k_interior_copy(const double* __restrict__ x, double* __restrict__ y, Grid g) {
+// y = x on the interior, 0 on ghosts and pitch padding (5 variables); x and
+// y may alias (see above).
+__global__ void k_interior_copy(const double* x, double* y, Grid g) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= 5LL * g.vs) return;
   const int o = (int)(t % g.vs);

@@ -290,13 +290,48 @@ int les_device_bytes(const les_params* p, size_t* bytes) {
   return LES_OK;
 }
 
-int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, void* stream) {
+// Host table X[nx], R[nr], cos(theta)[nth], sin(theta)[nth] of a cylindrical
+// product mesh; the maps may be host or device arrays.  The angle functions
+// are those of the host C library, so a caller that forms its own
+// coordinates with the same functions gets the same mesh bitwise.
+static int product_table(const les_params* p, const double* X, const double* R, const double* TH,
+                         std::vector<double>& tab, std::string& why) {
+  const size_t nx = (size_t)p->nx, nr = (size_t)p->nr, nth = (size_t)p->nth;
+  tab.assign(nx + nr + 2 * nth, 0.0);
+  std::vector<double> th(nth);
+  hipError_t e = hipMemcpy(tab.data(), X, nx * sizeof(double), hipMemcpyDefault);
+  if (e == hipSuccess) e = hipMemcpy(tab.data() + nx, R, nr * sizeof(double), hipMemcpyDefault);
+  if (e == hipSuccess) e = hipMemcpy(th.data(), TH, nth * sizeof(double), hipMemcpyDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    why = std::string("reading the 1-D maps: ") + hipGetErrorString(e);
+    return LES_EHIP;
+  }
+  for (size_t k = 0; k < nx + nr; ++k)
+    if (!std::isfinite(tab[k])) { why = "X and R must be finite"; return LES_EINVAL; }
+  for (size_t k = 0; k < nth; ++k) {
+    if (!std::isfinite(th[k])) { why = "TH must be finite"; return LES_EINVAL; }
+    tab[nx + nr + k] = std::cos(th[k]);
+    tab[nx + nr + nth + k] = std::sin(th[k]);
+  }
+  return LES_OK;
+}
+
+int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, const double* X,
+                  const double* R, const double* TH, void* stream) {
   if (!out) return fail(nullptr, LES_EINVAL, "out is NULL");
   *out = nullptr;
   std::string why;
   int r = validate(p, why);
   if (r != LES_OK) return fail(nullptr, r, why);
-  if (!xyz) return fail(nullptr, LES_EINVAL, "xyz is NULL");
+  const bool maps = X || R || TH;
+  if (maps && !(X && R && TH)) return fail(nullptr, LES_EINVAL, "X, R and TH go together");
+  if (!xyz == !maps) return fail(nullptr, LES_EINVAL, "give either xyz or the maps X, R, TH");
+  std::vector<double> tab;
+  if (maps) {
+    r = product_table(p, X, R, TH, tab, why);
+    if (r != LES_OK) return fail(nullptr, r, why);
+  }
   les_ctx* c = new (std::nothrow) les_ctx();
   if (!c) return fail(nullptr, LES_ENOMEM, "host allocation failed");
   c->p = *p;
@@ -320,10 +355,19 @@ int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, void* s
   if (r == LES_OK) r = dalloc(c, (void**)&c->dt, sizeof(double), "dt");
   if (r == LES_OK) r = dalloc(c, (void**)&c->flag, sizeof(int), "flag");
   if (r != LES_OK) { t_err = c->err; free_all(c); delete c; return r; }
-  e = launch_coords(xyz, c->coords, c->cg, p->bc, p->period, s);
+  double* tab_d = nullptr;   // device copy of the product-mesh table (freed below)
+  e = hipSuccess;
+  if (maps) {
+    e = hipMalloc((void**)&tab_d, tab.size() * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tab_d, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess) e = launch_coords(xyz, tab_d, c->coords, c->cg, p->bc, p->period, s);
   if (e == hipSuccess) e = launch_reset(c->maxbits, c->flag, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (tab_d) (void)hipFree(tab_d);
   if (e != hipSuccess) {
+    (void)hipGetLastError();
     hip_fail(nullptr, e, "les_init_grid");
     free_all(c);
     delete c;
@@ -748,10 +792,15 @@ int les_profile_read(les_ctx* c, int64_t* launches, double* total_ms) {
   return LES_OK;
 }
 
-int les_query(const les_ctx* c, int64_t dims[3], int64_t* var_stride, size_t* device_bytes) {
+int les_query(const les_ctx* c, int64_t dims_padded[4], int64_t* pitch, size_t* device_bytes) {
   if (!c) return fail(nullptr, LES_EINVAL, "ctx is NULL");
-  if (dims) { dims[0] = c->p.nth + 2 * NG; dims[1] = c->p.nr + 2 * NG; dims[2] = c->g.pitch; }
-  if (var_stride) *var_stride = c->g.vs;
+  if (dims_padded) {
+    dims_padded[0] = 5;
+    dims_padded[1] = c->p.nth + 2 * NG;
+    dims_padded[2] = c->p.nr + 2 * NG;
+    dims_padded[3] = c->g.pitch;
+  }
+  if (pitch) *pitch = c->g.pitch;
   if (device_bytes) *device_bytes = c->bytes;
   return LES_OK;
 }

@@ -6,15 +6,25 @@
 
 namespace lesjet {
 
-// interior coordinates (3, nth, nr, nx) dense -> padded coordinate array
-__global__ void k_coord_copy(const double* __restrict__ xyz, double* __restrict__ C, CGrid g) {
+// Interior coordinates of a cylindrical product mesh into the padded
+// coordinate array: x = X_i, y = R_j cos(theta_k), z = R_j sin(theta_k).
+// tab = X[nx], R[nr], cos(theta)[nth], sin(theta)[nth] (the two tables of
+// the angles are formed on the host).
+__global__ void k_coord_product(const double* __restrict__ tab, double* __restrict__ C, CGrid g) {
+  const double* X = tab;
+  const double* R = X + g.nx;
+  const double* ct = R + g.nr;
+  const double* st = ct + g.nth;
   const long long n = (long long)g.nx * g.nr * g.nth;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
        t += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(t % g.nx);
     const int j = (int)((t / g.nx) % g.nr);
     const int k = (int)(t / ((long long)g.nx * g.nr));
-    for (int c = 0; c < 3; ++c) C[(long long)c * g.vs + g.at(i, j, k)] = xyz[c * n + t];
+    const int o = g.at(i, j, k);
+    C[o] = X[i];
+    C[(long long)g.vs + o] = R[j] * ct[k];
+    C[2LL * g.vs + o] = R[j] * st[k];
   }
 }
 
@@ -115,10 +125,25 @@ static unsigned grid_stride_blocks(long long n) {
   return (unsigned)(b > 65536 ? 65536 : (b < 1 ? 1 : b));
 }
 
-hipError_t launch_coords(const double* xyz, double* C, const CGrid& cg, const int bc[6],
-                         const double period[3][3], hipStream_t s) {
+hipError_t launch_coords(const double* xyz, const double* tab, double* C, const CGrid& cg,
+                         const int bc[6], const double period[3][3], hipStream_t s) {
   const long long n = (long long)cg.nx * cg.nr * cg.nth;
-  hipLaunchKernelGGL(k_coord_copy, dim3(grid_stride_blocks(n)), dim3(256), 0, s, xyz, C, cg);
+  if (xyz) {
+    // (3, nth, nr, nx) dense, host or device: one pitched copy per variable
+    // and plane (the runtime takes the direction from the addresses)
+    for (int c = 0; c < 3; ++c)
+      for (int k = 0; k < cg.nth; ++k) {
+        const double* src = xyz + (long long)c * n + (long long)k * cg.nx * cg.nr;
+        double* dst = C + (long long)c * cg.vs + cg.at(0, 0, k);
+        const hipError_t e = hipMemcpy2DAsync(dst, (size_t)cg.pitch * sizeof(double), src,
+                                              (size_t)cg.nx * sizeof(double),
+                                              (size_t)cg.nx * sizeof(double), (size_t)cg.nr,
+                                              hipMemcpyDefault, s);
+        if (e != hipSuccess) return e;
+      }
+  } else {
+    hipLaunchKernelGGL(k_coord_product, dim3(grid_stride_blocks(n)), dim3(256), 0, s, tab, C, cg);
+  }
   for (int d = 0; d < 3; ++d) {
     long long lines;
     if (d == 0) lines = (long long)cg.nr * cg.nth;

@@ -6,8 +6,11 @@
 
 namespace lesjet {
 
-hipError_t launch_coords(const double* xyz, double* C, const CGrid& cg, const int bc[6],
-                         const double period[3][3], hipStream_t s);
+// Padded coordinates with three ghost layers: from xyz (3, nth, nr, nx), host
+// or device, or (xyz NULL) from the device table of a cylindrical product
+// mesh X[nx], R[nr], cos(theta)[nth], sin(theta)[nth].
+hipError_t launch_coords(const double* xyz, const double* tab, double* C, const CGrid& cg,
+                         const int bc[6], const double period[3][3], hipStream_t s);
 
 template <typename T>
 hipError_t launch_metrics(const double* C, const CGrid& cg, T* M, const Grid& g, double* M64,

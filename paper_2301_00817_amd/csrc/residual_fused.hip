@@ -33,49 +33,12 @@ namespace lesjet {
 // blocks per CU); both measured fastest among 64x8, 32x8 and 16x16 on the
 // jet meshes.
 template <typename T> struct Tile;
-#if defined(LESJET_TILE64_X) && defined(LESJET_TILE64_Y) && defined(LESJET_TILE64_PER_CU)
-template <> struct Tile<double> {
-  static constexpr int X = LESJET_TILE64_X, Y = LESJET_TILE64_Y, PER_CU = LESJET_TILE64_PER_CU;
-};
-#else
 template <> struct Tile<double> { static constexpr int X = 16, Y = 16, PER_CU = 2; };
-#endif
-#if defined(LESJET_TILE32_X) && defined(LESJET_TILE32_Y) && defined(LESJET_TILE32_PER_CU)
-template <> struct Tile<float> {
-  static constexpr int X = LESJET_TILE32_X, Y = LESJET_TILE32_Y, PER_CU = LESJET_TILE32_PER_CU;
-};
-#else
 template <> struct Tile<float> { static constexpr int X = 32, Y = 8, PER_CU = 4; };
-#endif
 
 constexpr int NPQ = 8;                // G(5), lambda_bar, nu, V per direction
 
-// LDS buffers of the plane state: one (a second saves a barrier per plane,
-// but costs a block per CU in either precision).
-template <typename T> struct PlaneBuffers;
-#if defined(LESJET_DBUF32)
-template <> struct PlaneBuffers<float> { static constexpr int n = LESJET_DBUF32; };
-#else
-template <> struct PlaneBuffers<float> { static constexpr int n = 1; };
-#endif
-template <> struct PlaneBuffers<double> { static constexpr int n = 1; };
-
 enum { EPI_R = 0, EPI_RK = 1, EPI_RK_LAST = 2 };
-
-// In-plane faces: each face evaluated once (by the column on its + side,
-// results exchanged through LDS, one more barrier) instead of once from each
-// side: fewer instructions and registers (FP64 no longer spills, FP32 fits
-// 128 VGPRs for four blocks per CU); measured 11-14 % faster in FP64 and,
-// with the four blocks, 5-6 % in FP32.
-template <typename T> struct FaceOnce;
-#ifndef LESJET_FACE_ONCE64
-#define LESJET_FACE_ONCE64 1
-#endif
-#ifndef LESJET_FACE_ONCE32
-#define LESJET_FACE_ONCE32 1
-#endif
-template <> struct FaceOnce<double> { static constexpr bool on = LESJET_FACE_ONCE64 != 0; };
-template <> struct FaceOnce<float> { static constexpr bool on = LESJET_FACE_ONCE32 != 0; };
 
 template <typename T>
 __device__ __forceinline__ void load_q(const T* __restrict__ Q, const Grid& g, int i, int j, int k,
@@ -112,12 +75,6 @@ struct TileMap {
 // The FP64 kernel has registers left at two waves per SIMD: it loads Q^(0)
 // of the output point an iteration ahead (FP32 at 128 VGPRs does not).
 template <typename T> struct PrefetchQ0 { static constexpr bool on = sizeof(T) == 8; };
-#ifdef LESJET_PREF_Q0
-template <> struct PrefetchQ0<double> { static constexpr bool on = LESJET_PREF_Q0 != 0; };
-#endif
-#ifdef LESJET_PREF_Q0_32
-template <> struct PrefetchQ0<float> { static constexpr bool on = LESJET_PREF_Q0_32 != 0; };
-#endif
 
 // Wave priority: the FP64 kernel (two waves per SIMD, bound by latency)
 // raises its waves' issue priority from the face phase to the end of the
@@ -132,11 +89,7 @@ template <typename T> struct WavePrio { static constexpr bool on = sizeof(T) == 
 // Register budget: FP64 two waves per SIMD (242 VGPRs), FP32 four (128).
 template <typename T> struct FusedOcc;
 template <> struct FusedOcc<double> { static constexpr int waves = 2; };
-#ifdef LESJET_OCC32
-template <> struct FusedOcc<float> { static constexpr int waves = LESJET_OCC32; };
-#else
 template <> struct FusedOcc<float> { static constexpr int waves = 4; };
-#endif
 
 // AXIS: the eta- face is a centerline through mesh nodes (row j = 0 on the
 // axis); a separate instance so that the common case carries none of it.
@@ -164,17 +117,18 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   constexpr int FR_X = FB_X + 2;                // ring-2 tile
   constexpr int FR_Y = FB_Y + 2;
   constexpr int NBORDER = FR_X * FR_Y - FB_X * FB_Y;   // ring-2 points without a thread
-  // plane state and primitives; with two buffers (NB = 2) the next plane is
-  // written while the current one is still being read, saving a barrier
-  constexpr int NB = PlaneBuffers<T>::n;
-  __shared__ T sQb[NB][5][FR_Y][FR_X];
-  __shared__ T sPb[NB][5][FR_Y][FR_X];
+  // plane state and primitives (one buffer: a second would save a barrier
+  // per plane but costs a resident block per CU in either precision)
+  __shared__ T sQ[5][FR_Y][FR_X];
+  __shared__ T sP[5][FR_Y][FR_X];
   __shared__ T sX[NPQ][FB_Y][FB_X];
   __shared__ T sE[NPQ][FB_Y][FB_X];
-  constexpr bool ONCE = FaceOnce<T>::on;
-  // fluxes of the faces i - 1/2 (xi) and j - 1/2 (eta) of each column
-  __shared__ T sFx[ONCE ? 5 : 1][ONCE ? FB_Y : 1][ONCE ? FB_X : 1];
-  __shared__ T sFe[ONCE ? 5 : 1][ONCE ? FB_Y : 1][ONCE ? FB_X : 1];
+  // fluxes of the faces i - 1/2 (xi) and j - 1/2 (eta) of each column: each
+  // in-plane face is evaluated once, by the column on its + side, and read
+  // by both neighbours (evaluating it from both sides cost 11-14 % more time
+  // in FP64 and the registers of a fourth FP32 block per CU)
+  __shared__ T sFx[5][FB_Y][FB_X];
+  __shared__ T sFe[5][FB_Y][FB_X];
   __shared__ double sRed[(FB_X * FB_Y + 63) / 64];
 
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -203,14 +157,10 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   else { const int r = tid - 2 * FR_X; bry = 1 + (r >> 1); brx = (r & 1) ? FR_X - 1 : 0; }
   const int bi = i0 - 2 + brx, bj = j0 - 2 + bry;
 
-  // physical-boundary faces of this column
-  const bool phys_im = i == 0 && ph.phys_face[0][0];
-  const bool phys_ip = i == g.nx - 1 && ph.phys_face[0][1];
-  const bool phys_jm = j == 0 && ph.phys_face[1][0];
   const bool axis_row = AXIS && j == 0;      // centerline row (not advanced)
   const bool axis_face = AXIS && j == 1;     // face j - 1/2 is the axis face
-  const bool phys_jp = j == g.nr - 1 && ph.phys_face[1][1];
-  // the face i - 1/2 of column i = nx is the face nx - 1/2
+  // physical-boundary faces i - 1/2 and j - 1/2 of this column (the face
+  // i - 1/2 of column i = nx is the face nx - 1/2)
   const bool phys_xf = (i == 0 && ph.phys_face[0][0]) || (i == g.nx && ph.phys_face[0][1]);
   const bool phys_ef = (j == 0 && ph.phys_face[1][0]) || (j == g.nr && ph.phys_face[1][1]);
 
@@ -250,8 +200,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     prim5(q, ph, pc);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      sQb[0][c][ty + 1][tx + 1] = q[c];
-      sPb[0][c][ty + 1][tx + 1] = pc[c];
+      sQ[c][ty + 1][tx + 1] = q[c];
+      sP[c][ty + 1][tx + 1] = pc[c];
     }
     load_q(Qin, g, i, j, k0, Qd);
     prim5(Qd, ph, Pd);
@@ -267,18 +217,13 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     prim5(bq, ph, bp);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      sQb[0][c][bry][brx] = bq[c];
-      sPb[0][c][bry][brx] = bp[c];
+      sQ[c][bry][brx] = bq[c];
+      sP[c][bry][brx] = bp[c];
     }
   }
 
   for (int kk = k0 - 1; kk <= k1; ++kk) {
     const bool more = kk < k1;
-    const int cur = NB == 2 ? ((kk - k0 + 1) & 1) : 0;
-    T (*sQ)[FR_Y][FR_X] = sQb[cur];
-    T (*sP)[FR_Y][FR_X] = sPb[cur];
-    T (*nQ)[FR_Y][FR_X] = sQb[NB == 2 ? cur ^ 1 : 0];
-    T (*nP)[FR_Y][FR_X] = sPb[NB == 2 ? cur ^ 1 : 0];
     // own-column and metric loads of the next plane, in flight during (b)
     if (more) {
       if (kk + 2 <= k1 + 1) load_q(Qin, g, i, j, kk + 2, Qn);
@@ -353,7 +298,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
       for (int c = 0; c < 4; ++c) w[c] = sQ[c][yy][xx];
       w[4] = sQ[4][yy][xx] + sP[4][yy][xx];
     };
-    if (ONCE && kk >= k0 && kk < k1) {
+    if (kk >= k0 && kk < k1) {
       // in-plane faces of the output planes, one per column and direction
       T Wm[5], Wl[5], Wr[5], Wp[5], F[5], GA[5], GB[5];
       if (xface) {
@@ -382,56 +327,14 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
         for (int c = 0; c < 5; ++c) sFe[c][ty][tx] = F[c];
       }
     }
-    if (ONCE) __syncthreads();
+    __syncthreads();
     if (interior && kk >= k0) {
-      // in-plane faces (output planes only)
+      // flux differences of the in-plane faces (output planes only)
       T rhs[5] = {0, 0, 0, 0, 0};
-      if (ONCE && kk < k1) {
+      if (kk < k1) {
 #pragma unroll
         for (int c = 0; c < 5; ++c)
           rhs[c] = sFx[c][ty][tx + 1] - sFx[c][ty][tx] + sFe[c][ty + 1][tx] - sFe[c][ty][tx];
-      } else if (!ONCE && kk < k1) {
-        // sliding window along each in-plane direction: the face -1/2 uses
-        // points -2..1, the face +1/2 points -1..2
-        T Wm[5], Wl[5], Wr[5], Wp[5], Fm[5], Fp[5];
-        {
-          T GA[5], GB[5];
-          wload(ty + 1, tx - 1, Wm); wload(ty + 1, tx, Wl); wload(ty + 1, tx + 1, Wr);
-          wload(ty + 1, tx + 2, Wp);
-#pragma unroll
-          for (int c = 0; c < 5; ++c) { GA[c] = sX[c][ty][tx - 1]; GB[c] = sX[c][ty][tx]; }
-          face_flux(GA, GB, sX[5][ty][tx - 1], sX[5][ty][tx], sX[6][ty][tx - 1], sX[6][ty][tx],
-                    sX[7][ty][tx - 1], sX[7][ty][tx], Wm, Wl, Wr, Wp, phys_im, ph, Fm);
-          wload(ty + 1, tx + 3, Wm);       // reuse Wm as the point +2
-#pragma unroll
-          for (int c = 0; c < 5; ++c) GA[c] = sX[c][ty][tx + 1];
-          face_flux(GB, GA, sX[5][ty][tx], sX[5][ty][tx + 1], sX[6][ty][tx], sX[6][ty][tx + 1],
-                    sX[7][ty][tx], sX[7][ty][tx + 1], Wl, Wr, Wp, Wm, phys_ip, ph, Fp);
-#pragma unroll
-          for (int c = 0; c < 5; ++c) rhs[c] = Fp[c] - Fm[c];
-        }
-        {
-          T GA[5], GB[5];
-          // axis face: lambda_bar of row 1 and the three-point fourth
-          // difference W(2) - 4 W(1) + 3 W(0), i.e. the standard formula with
-          // W(-1) replaced by W(1); done by choosing the rows read
-          const int rm = AXIS && axis_face ? ty + 1 : ty - 1;
-          const int rl = AXIS && axis_face ? ty : ty - 1;
-          wload(rm, tx + 1, Wm); wload(ty, tx + 1, Wl); wload(ty + 1, tx + 1, Wr);
-          wload(ty + 2, tx + 1, Wp);
-#pragma unroll
-          for (int c = 0; c < 5; ++c) { GA[c] = sE[c][ty - 1][tx]; GB[c] = sE[c][ty][tx]; }
-          face_flux(GA, GB, sE[5][rl][tx], sE[5][ty][tx],
-                    sE[6][ty - 1][tx], sE[6][ty][tx], sE[7][ty - 1][tx], sE[7][ty][tx],
-                    Wm, Wl, Wr, Wp, phys_jm, ph, Fm);
-          wload(ty + 3, tx + 1, Wm);
-#pragma unroll
-          for (int c = 0; c < 5; ++c) GA[c] = sE[c][ty + 1][tx];
-          face_flux(GB, GA, sE[5][ty][tx], sE[5][ty + 1][tx], sE[6][ty][tx], sE[6][ty + 1][tx],
-                    sE[7][ty][tx], sE[7][ty + 1][tx], Wl, Wr, Wp, Wm, phys_jp, ph, Fp);
-#pragma unroll
-          for (int c = 0; c < 5; ++c) rhs[c] += Fp[c] - Fm[c];
-        }
       }
       // zeta face kk-1/2: L = kk-1 (registers), R = kk
       T Wc[5], Wd[5], Fk[5];
@@ -487,17 +390,15 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     lbz = po.lb[2];
     nuz = po.nu[2];
     Vz = in.V;
-    // plane kk is read by other threads until here; with the faces evaluated
-    // once, the barrier after the face fluxes already orders those reads
-    // (what follows reads only the thread's own column, which the next
-    // plane's border writes never touch)
-    if (NB == 1 && !ONCE) __syncthreads();
+    // plane kk is read by other threads until the barrier after the face
+    // fluxes; what follows reads only the thread's own column, which the
+    // next plane's border writes never touch
     if (more) {
       // plane kk+1 goes to LDS: own column and ring-2 border
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        nQ[c][ty + 1][tx + 1] = Qd[c];
-        nP[c][ty + 1][tx + 1] = Pd[c];
+        sQ[c][ty + 1][tx + 1] = Qd[c];
+        sP[c][ty + 1][tx + 1] = Pd[c];
         Qd[c] = Qn[c];
       }
       if (has_b) {
@@ -505,8 +406,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
         prim5(Bn, ph, bp);
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-          nQ[c][bry][brx] = Bn[c];
-          nP[c][bry][brx] = bp[c];
+          sQ[c][bry][brx] = Bn[c];
+          sP[c][bry][brx] = bp[c];
         }
       }
       prim5(Qd, ph, Pd);

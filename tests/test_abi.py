@@ -19,10 +19,16 @@ def _declared():
     return sorted(set(re.findall(r"\b(les_[a-z0-9_]+)\s*\(", text)))
 
 
+# the five calls of the boundary, the step adjoint and the calls every
+# caller needs around them
+REQUIRED = ("les_init_grid", "les_metrics", "les_residual", "les_rk5_step", "les_residual_vjp",
+            "les_rk5_step_vjp", "les_set_inflow", "les_query", "les_last_error", "les_free")
+
+
 def test_header_declares_the_boundary():
     names = _declared()
-    for required in ("les_init_grid", "les_metrics", "les_residual", "les_rk5_step"):
-        assert required in names
+    for required in REQUIRED:
+        assert required in names, required
 
 
 def test_library_exports_every_declared_symbol():
@@ -30,7 +36,9 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(binding.LIB_PATH)
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
-    assert set(binding.EXPORTS) <= set(_declared())
+    for n in REQUIRED:
+        assert hasattr(lib, n), n
+    assert set(binding.EXPORTS) == set(_declared())
 
 
 def _params(**over):
@@ -85,11 +93,18 @@ def test_layout_refuses_oversized_variable():
     assert e.value.code == B.LES_EUNSUPPORTED
 
 
-def test_init_grid_rejects_null_before_device_work():
+def test_init_grid_rejects_bad_mesh_arguments_before_device_work():
+    """Neither form, both forms, or only some of the 1-D maps: LES_EINVAL
+    before the runtime is touched (no GPU here)."""
     from paper_2301_00817_amd import binding as B
-    with pytest.raises(B.LesError) as e:
-        B.les_init_grid(_params(), None)
-    assert e.value.code == B.LES_EINVAL
+    buf = (ctypes.c_double * 8)()
+    a = ctypes.addressof(buf)
+    for args in [(None, None, None, None), (a, a, a, a), (None, a, a, None), (None, None, a, a),
+                 (a, a, None, None)]:
+        with pytest.raises(B.LesError) as e:
+            B.les_init_grid(_params(), *args)
+        assert e.value.code == B.LES_EINVAL, args
+        assert B.les_last_error(None)
 
 
 def test_big_mesh_layout_fits_32bit_offsets():

@@ -40,7 +40,7 @@ def test_call_order_and_arguments():
     p = B.make_params(pb["params"], (12, 8, 8), B.LES_FP64)
     xyz = pb["xyz"].cuda().contiguous()
     stream = torch.cuda.current_stream().cuda_stream
-    ctx = B.les_init_grid(p, xyz.data_ptr(), stream)
+    ctx = B.les_init_grid(p, xyz.data_ptr(), None, None, None, stream)
     try:
         _, dims, _ = B.les_layout(p)
         Q = torch.zeros((5,) + dims, dtype=torch.float64, device="cuda")

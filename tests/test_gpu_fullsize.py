@@ -1,5 +1,6 @@
 """Parity at the measured sizes, in the configuration bench.py times (the
-same workload generator, precision and launch shapes), on sampled outputs.
+same workload generator — the mesh built by the library from its 1-D maps —
+precision and launch shapes), on sampled outputs.
 
 The residual at an interior point depends only on the state and coordinates
 within two points of it (point quantities at the neighbours need their
@@ -7,16 +8,21 @@ central differences, faces need W two points out); after one RK5 step the
 state at a point depends on the initial data within ten points.  So the
 oracle, run on a small block cut out around a sampled point (any boundary
 kind: its ghosts never reach the centre), gives the exact full-mesh value
-there.  Points are sampled at least the block half-width away from the
-physical boundaries (the azimuth wraps).
+there.  The block's coordinates are formed on the host from the same 1-D
+maps and the same C-library angle functions the library uses, so they are
+the library's coordinates bitwise.  Points are sampled at least the block
+half-width away from the physical boundaries (the azimuth wraps).
 
-Bars: FP64 residual 1e-12 of the full field's max per group; FP32-storage
-residual 1e-3; FP64 state after one step 1e-11."""
+Norms (see _helpers; per-variable errors relative to the full field's max
+are printed): FP64 residual 1e-13 of the flux scale at the sampled points
+per variable and 1e-12 in the vector norm; FP32-storage residual 1e-3 per
+variable; FP64 state after one step 1e-11 per variable."""
 import numpy as np
 import pytest
 import torch
 
-from _helpers import announce, grouped_rel_err
+from _helpers import announce, report
+from cases import mesh
 from oracle import les
 
 pytestmark = pytest.mark.gpu
@@ -26,12 +32,12 @@ def _workload(config, precision):
     import bench
     from paper_2301_00817_amd.solver import Solver
     dev = torch.device("cuda:0")
-    prm, xyz, fill, inflow = bench.make_workload(config, dev)
-    s = Solver(prm, xyz, inflow, precision=precision, device=dev)
+    prm, msh, fill, inflow = bench.make_workload(config, dev)
+    s = Solver(prm, inflow=inflow, precision=precision, device=dev, **msh)
     Qn = s.field(5, dtype=torch.float64, fill=0.0)
     fill(s.interior(Qn))
     torch.cuda.synchronize()
-    return prm, xyz, s, Qn
+    return prm, msh["grid"], s, Qn
 
 
 def _samples(shape, n, h, seed):
@@ -41,14 +47,25 @@ def _samples(shape, n, h, seed):
             for _ in range(n)]
 
 
+def _ks(k, h, nth):
+    return [(k + d) % nth for d in range(-h, h + 1)]
+
+
 def _block(A, p, h):
     """(c, 2h+1, 2h+1, 2h+1) block of an interior-indexed device array
     (c, nth, nr, nx) around p = (i, j, k), k wrapped; as NumPy FP64."""
     i, j, k = p
-    nth = A.shape[1]
-    ks = torch.tensor([(k + d) % nth for d in range(-h, h + 1)], device=A.device)
-    B = A.index_select(1, ks)[:, :, j - h:j + h + 1, i - h:i + h + 1]
+    ks = torch.tensor(_ks(k, h, A.shape[1]), device=A.device)
+    B = A[:, :, j - h:j + h + 1, i - h:i + h + 1].index_select(1, ks)
     return B.to(torch.float64).cpu().numpy()
+
+
+def _block_xyz(grid, p, h):
+    """Coordinates of the block from the 1-D maps (host, C-library angles)."""
+    X, R, TH = grid
+    i, j, k = p
+    th = TH[torch.tensor(_ks(k, h, TH.numel()))]
+    return mesh.cylindrical_coords(X[i - h:i + h + 1], R[j - h:j + h + 1], th).numpy()
 
 
 def _block_params(prm):
@@ -57,49 +74,72 @@ def _block_params(prm):
     return dict(prm, bc=("periodic",) * 6, period=((0.0, 0.0, 0.0),) * 3)
 
 
-def _oracle_residual_at(prm, xyz_b, Q_b, h):
+def _oracle_at(prm, xyz_b, Q_b, h):
+    """The oracle's residual at the block centre and the flux scale there,
+    sum over its six faces of |F_v| / |J^-1|."""
     pb = _block_params(prm)
     with np.errstate(all="ignore"):
         geo = les.geometry(xyz_b, pb)
-        R = les.evaluate(Q_b, geo, pb)
-    return R[:, h, h, h]
+        Qp = les.pad_state(Q_b)
+        les.fill_ghosts(Qp, geo, pb)
+        pt = les.point_terms(Qp, geo, pb)
+        R = les.residual(Qp, geo, pb)
+        acc = np.zeros(5)
+        for d in range(3):
+            F = les.face_fluxes(pt, d, pb)      # faces -1/2 .. n-1/2 along the last axis
+            Fc = np.moveaxis(F, -1, F.ndim - 1 - d)
+            # the two faces of the centre along d: indices h and h + 1 of the face axis
+            sl_lo = [slice(None), h, h, h]
+            sl_hi = [slice(None), h, h, h]
+            sl_lo[3 - d] = h
+            sl_hi[3 - d] = h + 1
+            acc += np.abs(Fc[tuple(sl_lo)]) + np.abs(Fc[tuple(sl_hi)])
+        V = abs(float(les.interior(geo["V"])[h, h, h]))
+    return R[:, h, h, h], acc / V
 
 
-def _group_scale(R):
-    """max |R| per group (mass, momentum, energy) over the whole field."""
-    a = R.abs()
-    return np.array([float(a[0].max()), float(a[1:4].max()), float(a[4].max())])
-
-
-def _grouped_point_err(got, ref, scale):
-    e = np.abs(np.asarray(got) - np.asarray(ref))
-    return max(e[:, 0].max() / scale[0], e[:, 1:4].max() / scale[1], e[:, 4].max() / scale[2])
-
-
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("config,precision,nsamp", [("jet5.9M", "fp64", 48),
                                                     ("jet5.9M", "fp32", 48),
-                                                    ("big1B", "fp64", 24)])
+                                                    ("big1B", "fp64", 24),
+                                                    ("big1B", "fp32", 24)])
 def test_sampled_residual(config, precision, nsamp):
     announce("fullsize-residual", config, precision)
-    prm, xyz, s, Qn = _workload(config, precision)
+    prm, grid, s, Qn = _workload(config, precision)
     Qp = Qn if precision == "fp64" else Qn.to(torch.float32)
+    if precision == "fp32":
+        del Qn
+        torch.cuda.empty_cache()
     R = s.residual(Qp)
     Ri = s.interior(R)
-    scale = _group_scale(Ri)
+    vmax = np.array([float(Ri[v].abs().max()) for v in range(5)])
+    mmag = float(torch.sqrt((Ri[1:4].double() ** 2).sum(dim=0)).max())
     Qi = s.interior(Qp)
     h = 2
     pts = _samples(s.shape, nsamp, h + 1, seed=7)
-    got, ref = [], []
+    got, ref, fsc = [], [], []
     for p in pts:
         i, j, k = p
         got.append(Ri[:, k, j, i].to(torch.float64).cpu().numpy())
-        ref.append(_oracle_residual_at(prm, _block(xyz, p, h), _block(Qi, p, h), h))
-    err = _grouped_point_err(got, ref, scale)
-    print(f"{config} {precision}: sampled residual rel err {err:.3e} over {len(pts)} points")
-    assert np.isfinite(np.asarray(got)).all()
-    assert err <= (1e-12 if precision == "fp64" else 1e-3)
+        r, f = _oracle_at(prm, _block_xyz(grid, p, h), _block(Qi, p, h), h)
+        ref.append(r)
+        fsc.append(f)
+    got, ref, fsc = np.array(got), np.array(ref), np.array(fsc)
+    e = np.abs(got - ref).max(axis=0)
+    pv = e / vmax
+    vn = pv.copy()
+    vn[1:4] = e[1:4] / mmag
+    fx = e / fsc.max(axis=0)
+    report(f"{config} {precision} sampled residual ({len(pts)} points)", per_variable=pv,
+           vector=vn, flux=fx)
+    assert np.isfinite(got).all()
+    if precision == "fp64":
+        assert fx.max() <= 1e-13
+        assert vn.max() <= 1e-12
+    else:
+        assert pv.max() <= 1e-3
     s.close()
-    del R, Qp, Qn, xyz
+    del R, Ri, Qp, Qi
     torch.cuda.empty_cache()
 
 
@@ -107,7 +147,7 @@ def test_sampled_rk5_step_jet5p9M():
     """One CFL step of the 288 x 160 x 128 workload; the state at sampled
     points against the oracle's step of a 23^3 block with the same dt."""
     announce("fullsize-rk5", "jet5.9M", "fp64")
-    prm, xyz, s, Qn = _workload("jet5.9M", "fp64")
+    prm, grid, s, Qn = _workload("jet5.9M", "fp64")
     Q0 = s.interior(Qn).clone()
     dt = float(s.rk5_step(Qn, 1)[0])
     Q1 = s.interior(Qn)
@@ -119,13 +159,14 @@ def test_sampled_rk5_step_jet5p9M():
         i, j, k = p
         got.append(Q1[:, k, j, i].cpu().numpy())
         with np.errstate(all="ignore"):
-            geo = les.geometry(_block(xyz, p, h), pb)
+            geo = les.geometry(_block_xyz(grid, p, h), pb)
             Qb, _ = les.rk5_step(_block(Q0, p, h), geo, pb, None, dt)
         ref.append(Qb[:, h, h, h])
-    scale = _group_scale(Q1)
-    err = _grouped_point_err(got, ref, scale)
-    print(f"jet5.9M: sampled state after one step rel err {err:.3e}")
-    assert err <= 1e-11
+    got, ref = np.array(got), np.array(ref)
+    vmax = np.array([float(Q1[v].abs().max()) for v in range(5)])
+    pv = np.abs(got - ref).max(axis=0) / vmax
+    report("jet5.9M sampled state after one step", per_variable=pv)
+    assert pv.max() <= 1e-11
     s.close()
-    del Qn, Q0, xyz
+    del Qn, Q0
     torch.cuda.empty_cache()

@@ -88,15 +88,21 @@ def test_functional_gradient_tiny_jet_against_oracle():
     geo = les.geometry(pb["xyz"].numpy(), prm)
     dt = 0.5 * float(les.time_step(pb["Q"].numpy(), geo, prm))
     surf = ofun.surface(X.numpy(), R.numpy(), nth, 0.5)
-    J_or = None
+    surf6 = ofun.surface(X.numpy(), R.numpy(), nth, 6.0)
+    J_or = J6_or = None
     g_or = np.empty(NC)
+    g6_or = np.empty(NC)
     for c in range(NC):
         coef = torch.zeros(NC, dtype=torch.complex128)
         coef[c] = 1j * H_CS
         Q0, inflow = _inputs(grid, seed, coef, "cpu")
         J, _ = ofun.rollout(Q0.numpy(), geo, prm, inflow.numpy(), dt, nsteps, surf, prm["p_exit"])
+        J6, _ = ofun.rollout(Q0.numpy(), geo, prm, inflow.numpy(), dt, nsteps, surf6,
+                             prm["p_exit"])
         g_or[c] = np.imag(J) / H_CS
+        g6_or[c] = np.imag(J6) / H_CS
         J_or = float(np.real(J))
+        J6_or = float(np.real(J6))
     from paper_2301_00817_amd import adjoint as A
     s = make_solver(pb)
     fn = A.SurfacePressure(pb["xyz"], 0.5, prm["p_exit"], prm["gamma"])
@@ -113,6 +119,18 @@ def test_functional_gradient_tiny_jet_against_oracle():
     assert np.abs(g1 - g5).max() <= 1e-14 * np.abs(g5).max()
     assert errJ <= 1e-12
     assert err <= 1e-10
+    # the functional on the r = 6 D surface (on this coarse mesh the RK5
+    # stencil, ten points per step, spans the radial range within a step, so
+    # its gradient is well above rounding and the complex step resolves it)
+    fn6 = A.SurfacePressure(pb["xyz"], 6.0, prm["p_exit"], prm["gamma"])
+    assert fn6.js == surf6[0] and surf6[0] != surf[0]
+    J6g, g6 = _gpu_J_and_grad(s, pb, grid, seed, dt, nsteps, 5, fn6)
+    err6 = np.abs(g6 - g6_or).max() / np.abs(g6_or).max()
+    print("tiny 6D: J %.6e (oracle %.6e); |g| %.3e rel err %.3e"
+          % (J6g, J6_or, np.abs(g6_or).max(), err6))
+    assert np.abs(g6_or).max() > 0.0
+    assert abs(J6g - J6_or) <= 1e-12 * abs(J6_or)
+    assert err6 <= 1e-10
 
 
 def test_functional_gradient_full_mesh_against_differences():
@@ -133,6 +151,13 @@ def test_functional_gradient_full_mesh_against_differences():
     print("dt %.4e; J(0.5D) %.6e |g|max %.3e; J(6D) %.3e |g6|max %.3e"
           % (dt, J, np.abs(g).max(), J6, np.abs(g6).max()))
     assert np.all(np.isfinite(g6))
+    # Reading R34: after 20 steps (t ~ 2.4e-3) no acoustic signal from the
+    # shear layer has reached r = 6 D (about 5.5 D away); what the discrete
+    # stencil carries across the 38 radial cells in between decays by orders
+    # of magnitude per cell, so the 6 D gradient must sit far below that of
+    # the lip-line functional (measured about 1e-37 against O(1e-3)).  A
+    # regression leaking sensitivity to the far surface would break this.
+    assert np.abs(g6).max() <= 1e-20 * np.abs(g).max()
     best = None
     for h in (1e-3, 1e-4, 1e-5):
         fd = np.empty(NC)

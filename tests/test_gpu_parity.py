@@ -2,29 +2,45 @@
 C-ABI: metrics, ghost fill, residual, time step and RK5 steps, on grids that
 span several tiles with ragged tails, plus properties at full size.
 
-Bars (FP64): metrics and copied ghosts agree to rounding (1e-14 relative);
-the residual to 1e-12 of its max per group (mass, momentum, energy); the
-state after 10 RK5 steps to 1e-11, after 100 steps (the jet workload's run
+Bars (FP64; the norms are described in _helpers): metrics and copied ghosts
+agree to rounding (1e-14 relative); the residual to 1e-13 of its flux scale
+per variable (the face fluxes whose differences form it: rounding of a
+difference is bounded relative to the terms, not to the difference) and to
+1e-12 of its max (momentum over the vector's magnitude); the state after
+10 RK5 steps to 1e-11 per variable, after 100 steps (the jet workload's run
 length, on a mesh the oracle steps in seconds) to 1e-10: rounding
-differences grow at most linearly with the number of steps.  The GPU contracts multiply-adds and
-uses reciprocal multiplies where the oracle divides, so agreement is to a
-few ulps of the flux scale, amplified by the cancellation in flux
-differences."""
+differences grow at most linearly with the number of steps.  The GPU
+contracts multiply-adds and uses reciprocal multiplies where the oracle
+divides, so agreement is to a few ulps of the flux scale.  Every test
+prints the per-variable errors (relative to each variable's own max)."""
 import math
 
 import numpy as np
 import pytest
 import torch
 
-from _helpers import announce, grouped_rel_err, make_solver, to_np
+from _helpers import (announce, flux_err, flux_scale, grouped_rel_err, make_solver,
+                      per_variable_err, report, to_np, vector_err)
 from cases import problems
 from oracle import les
 
 pytestmark = pytest.mark.gpu
 
-R_BAR = 1e-12
-Q_BAR = 1e-11
+R_BAR = 1e-12          # vector norm (P1) of the residual
+R_FLUX_BAR = 1e-13     # residual over its flux scale (P2), per variable
+Q_BAR = 1e-11          # per variable
 Q_BAR_100 = 1e-10
+
+
+def check_residual(label, R, R_ref, Q, geo, prm, inflow):
+    """Assert the FP64 residual bars; print all three norms."""
+    pv = per_variable_err(R, R_ref)
+    vn = vector_err(R, R_ref)
+    fx = flux_err(R, R_ref, flux_scale(Q, geo, prm, inflow))
+    report(label + " residual", per_variable=pv, vector=vn, flux=fx)
+    assert np.isfinite(R).all()
+    assert fx.max() <= R_FLUX_BAR
+    assert vn.max() <= R_BAR
 
 
 def _oracle(pb):
@@ -92,7 +108,7 @@ def test_ghost_fill_matches_oracle_and_defines_every_point(name):
     torch.cuda.synchronize()
     Gn = to_np(G)[..., :s.shape[0] + 4]
     assert np.isfinite(Gn).all()
-    assert grouped_rel_err(Gn, Qp) <= 1e-14
+    assert grouped_rel_err(Gn, Qp, label=f"{name} ghosts") <= 1e-14
     s.close()
 
 
@@ -105,10 +121,7 @@ def test_residual_matches_oracle(name):
     s = make_solver(pb)
     Qp = s.pad(pb["Q"].cuda())
     R = to_np(s.interior(s.residual(Qp)))
-    assert np.isfinite(R).all()
-    err = grouped_rel_err(R, R_ref)
-    print(f"{name}: residual rel err {err:.3e}")
-    assert err <= R_BAR
+    check_residual(name, R, R_ref, pb["Q"].numpy(), geo, pb["params"], inflow)
     s.close()
 
 
@@ -136,9 +149,9 @@ def test_rk5_steps_match_oracle(name, steps):
     dt = to_np(s.rk5_step(Qn, steps))
     Q = to_np(s.interior(Qn))
     assert np.allclose(dt, dts, rtol=1e-12, atol=0)
-    err = grouped_rel_err(Q, Q_ref)
-    print(f"{name}: Q after {steps} steps rel err {err:.3e}")
-    assert err <= (Q_BAR if steps <= 10 else Q_BAR_100)
+    pv = per_variable_err(Q, Q_ref)
+    report(f"{name} Q after {steps} steps", per_variable=pv, vector=vector_err(Q, Q_ref))
+    assert pv.max() <= (Q_BAR if steps <= 10 else Q_BAR_100)
     s.close()
 
 
@@ -167,9 +180,7 @@ def test_residual_2M_jet_matches_oracle():
     s = make_solver(pb)
     Qp = s.pad(pb["Q"].cuda())
     R = to_np(s.interior(s.residual(Qp)))
-    err = grouped_rel_err(R, R_ref)
-    print(f"2M: residual rel err {err:.3e}")
-    assert err <= R_BAR
+    check_residual("jet160x100x128", R, R_ref, pb["Q"].numpy(), geo, pb["params"], inflow)
     s.close()
 
 
@@ -205,16 +216,19 @@ def test_residual_chunk_boundaries(kchunk, monkeypatch):
     R_ref = les.evaluate(pb["Q"].numpy(), geo, pb["params"], inflow)
     s = make_solver(pb)
     R = to_np(s.interior(s.residual(s.pad(pb["Q"].cuda()))))
-    assert grouped_rel_err(R, R_ref) <= R_BAR
+    check_residual(f"jet37x22x20 kchunk {kchunk}", R, R_ref, pb["Q"].numpy(), geo, pb["params"],
+                   inflow)
     s.close()
 
 
 @pytest.mark.parametrize("shape", [(288, 160, 128), (401, 97, 64)])
 def test_fused_matches_two_pass_reference(shape):
-    """Fused kernel against the two-pass reference kernels on full-size and
-    ragged jet meshes (no oracle at this size; both are GPU, independent
-    code paths sharing only the point and face formulas, compiled with
-    different multiply-add contraction, hence the 1e-13 bar)."""
+    """Consistency of the fused kernel with the two-pass reference kernels on
+    full-size and ragged jet meshes.  Both are GPU code sharing the point and
+    face formulas, so this is not parity evidence (the sampled oracle
+    comparisons at these sizes are): it checks the tiling, the march and the
+    halo handling of the fused kernel against plain indexing, to 1e-13 (the
+    two are compiled with different multiply-add contraction)."""
     announce("fused-vs-ref", shape)
     pb = problems.jet_problem(*shape, seed=2)
     s = make_solver(pb)
@@ -222,7 +236,7 @@ def test_fused_matches_two_pass_reference(shape):
     R1 = s.interior(s.residual(Qp)).clone()
     R2 = s.interior(s.residual_reference(Qp))
     torch.cuda.synchronize()
-    err = grouped_rel_err(to_np(R1), to_np(R2))
+    err = grouped_rel_err(to_np(R1), to_np(R2), label=f"fused vs two-pass {shape}")
     print(f"{shape}: fused vs reference {err:.3e}")
     assert err <= 1e-13
     s.close()

@@ -27,8 +27,9 @@ namespace lesjet {
 
 #if defined(__HIP_DEVICE_COMPILE__) && !defined(LESJET_IEEE_F64)
 // FP64 square root and reciprocal from the hardware estimates refined by
-// Newton-Raphson (Goldschmidt for the root): within an ulp or two of the
-// correctly rounded results, for positive finite arguments (sqrt(0) = 0),
+// Newton-Raphson (Goldschmidt for the root): within an ulp of the correctly
+// rounded results over the arguments the kernels meet (reciprocals of
+// |x| in [1e-13, 1e6], either sign; roots of [1e-20, 1e12]; sqrt(0) = 0),
 // at about half the instructions of the IEEE sequences (-DLESJET_IEEE_F64
 // restores those).
 __device__ __forceinline__ double nr_rcp(double x) {
@@ -59,9 +60,10 @@ template <> __host__ __device__ __forceinline__ double tsqrt<double>(double x) {
 #else
 template <> __host__ __device__ __forceinline__ double tsqrt<double>(double x) { return sqrt(x); }
 #endif
-// FP32 (the storage form only): the hardware square root and a cube root
-// from the hardware base-2 logarithm and exponential, each within a few ulps
-// of FP32, far inside that form's tolerances.
+// FP32 (the storage form only): the hardware square root (within an ulp)
+// and a cube root from the hardware base-2 logarithm and exponential (within
+// 4e-6 relative over the filter widths of the meshes), far inside that
+// form's tolerances.
 #if defined(__HIP_DEVICE_COMPILE__) && !defined(LESJET_IEEE_F32)
 template <> __host__ __device__ __forceinline__ float tsqrt<float>(float x) {
   return __builtin_amdgcn_sqrtf(x);

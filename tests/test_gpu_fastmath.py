@@ -14,8 +14,10 @@ that mesh), strain invariants and spectral-radius products, so x in
 
 FP32 (the FP32-storage form only): hardware reciprocal and square root,
 within 1 ulp; cube root as exp2(log2(x) / 3) from the hardware base-2
-logarithm and exponential, within 4 ulp (the filter width |J^-1|^(1/3),
-x in [1e-13, 1e6])."""
+logarithm and exponential, within 32 ulp (4e-6 relative: the absolute
+error of the logarithm, about an ulp of log2(x), becomes a relative error
+of the result that grows with |log2 x|; 22 ulp measured at x near 1e-13),
+for the filter width |J^-1|^(1/3), x in [1e-13, 1e6]."""
 import ctypes
 import os
 
@@ -91,4 +93,4 @@ def test_fp32_reciprocal_root_and_cube_root():
           f"cbrt max {u_cbrt.max()} ulp")
     assert u_rcp.max() <= 1
     assert u_sqrt.max() <= 1
-    assert u_cbrt.max() <= 4
+    assert u_cbrt.max() <= 32

@@ -97,8 +97,8 @@ def test_functional_gradient_tiny_jet_against_oracle():
         coef[c] = 1j * H_CS
         Q0, inflow = _inputs(grid, seed, coef, "cpu")
         J, _ = ofun.rollout(Q0.numpy(), geo, prm, inflow.numpy(), dt, nsteps, surf, prm["p_exit"])
-        J6, _ = ofun.rollout(Q0.numpy(), geo, prm, inflow.numpy(), dt, nsteps, surf6,
-                             prm["p_exit"])
+        J6, QN6 = ofun.rollout(Q0.numpy(), geo, prm, inflow.numpy(), dt, nsteps, surf6,
+                               prm["p_exit"])
         g_or[c] = np.imag(J) / H_CS
         g6_or[c] = np.imag(J6) / H_CS
         J_or = float(np.real(J))
@@ -121,16 +121,25 @@ def test_functional_gradient_tiny_jet_against_oracle():
     assert err <= 1e-10
     # the functional on the r = 6 D surface (on this coarse mesh the RK5
     # stencil, ten points per step, spans the radial range within a step, so
-    # its gradient is well above rounding and the complex step resolves it)
+    # its gradient is well above rounding and the complex step resolves it).
+    # There p - p_inf is about 1e-7 of p: the rounding of p (an ulp of p,
+    # formed from O(1) conserved variables) is a relative error of
+    # u p / |p - p_inf| in each term, so the bar is that conditioning times
+    # 64 ulps, taken from the oracle's final surface pressures.
     fn6 = A.SurfacePressure(pb["xyz"], 6.0, prm["p_exit"], prm["gamma"])
     assert fn6.js == surf6[0] and surf6[0] != surf[0]
     J6g, g6 = _gpu_J_and_grad(s, pb, grid, seed, dt, nsteps, 5, fn6)
+    p6 = les.primitives(np.real(QN6)[:, :, surf6[0], :], prm["gamma"])[4]
+    kappa = np.abs(p6).max() / np.abs(p6 - prm["p_exit"]).max()
+    bar6 = 64 * np.finfo(np.float64).eps * kappa
+    errJ6 = abs(J6g - J6_or) / abs(J6_or)
     err6 = np.abs(g6 - g6_or).max() / np.abs(g6_or).max()
-    print("tiny 6D: J %.6e (oracle %.6e); |g| %.3e rel err %.3e"
-          % (J6g, J6_or, np.abs(g6_or).max(), err6))
+    print("tiny 6D: J %.6e (oracle %.6e, rel %.2e); |g| %.3e rel err %.3e; "
+          "p/(p - p_inf) %.2e, bar %.2e" % (J6g, J6_or, errJ6, np.abs(g6_or).max(), err6, kappa,
+                                            bar6))
     assert np.abs(g6_or).max() > 0.0
-    assert abs(J6g - J6_or) <= 1e-12 * abs(J6_or)
-    assert err6 <= 1e-10
+    assert errJ6 <= bar6
+    assert err6 <= bar6
 
 
 def test_functional_gradient_full_mesh_against_differences():

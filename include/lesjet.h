@@ -305,6 +305,21 @@ int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, 
 int les_diagnostics(les_ctx* c, const double* Qn, double* totals, double* sum1, double* sum2,
                     void* stream);
 
+/* The same diagnostics as les_diagnostics, allocating nothing: for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or time-stepping loops, harnesses that forbid allocation).  The
+ * per-block partial sums of the totals go to a static device array of the
+ * library (80 KiB, at most 2048 blocks x 5 sums; every GPU the library runs
+ * on holds one until the process ends) instead of a buffer allocated on
+ * first use.  Sizes: any mesh the context accepts (the totals use at most
+ * 2048 partial sums); LES_EUNSUPPORTED if a mesh needed more.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads, other contexts) race and must be serialised
+ * by the caller.  Each call writes every partial sum before reading it, so
+ * the array's previous contents never matter.  Asynchronous on `stream`. */
+int les_diagnostics_noalloc(les_ctx* c, const double* Qn, double* totals, double* sum1,
+                            double* sum2, void* stream);
+
 /* Measurement support.  While enabled, every launch of the residual stage
  * kernel issued by les_residual and les_rk5_step is bracketed by a pair of
  * HIP events recorded on the call's stream, so the durations are those of

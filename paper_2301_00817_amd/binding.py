@@ -88,6 +88,7 @@ def _load():
         "les_residual_vjp": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "les_rk5_step_vjp": ([vp, vp, dbl, vp, vp, vp, vp], ctypes.c_int),
         "les_diagnostics": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "les_diagnostics_noalloc": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "les_profile": ([vp, i32], ctypes.c_int),
         "les_profile_read": ([vp, P(i64), P(dbl)], ctypes.c_int),
         "les_query": ([vp, P(i64 * 4), P(i64), P(sz)], ctypes.c_int),
@@ -105,7 +106,8 @@ _lib = _load()
 EXPORTS = ("les_validate", "les_layout", "les_device_bytes", "les_init_grid", "les_metrics",
            "les_set_inflow", "les_fill_ghosts", "les_residual", "les_residual_reference",
            "les_dynamic_coefficients",
-           "les_rk5_step", "les_residual_vjp", "les_rk5_step_vjp", "les_diagnostics", "les_profile",
+           "les_rk5_step", "les_residual_vjp", "les_rk5_step_vjp", "les_diagnostics",
+           "les_diagnostics_noalloc", "les_profile",
            "les_profile_read", "les_query",
            "les_last_error", "les_free")
 
@@ -188,6 +190,11 @@ def les_rk5_step_vjp(ctx, qn_ptr, dt, qbar_np1_ptr, qbar_n_ptr, inflow_bar_ptr=N
 
 def les_diagnostics(ctx, qn_ptr, totals_ptr=None, sum1_ptr=None, sum2_ptr=None, stream=0):
     return _check(_lib.les_diagnostics(ctx, qn_ptr, totals_ptr, sum1_ptr, sum2_ptr, stream), ctx)
+
+
+def les_diagnostics_noalloc(ctx, qn_ptr, totals_ptr=None, sum1_ptr=None, sum2_ptr=None, stream=0):
+    return _check(_lib.les_diagnostics_noalloc(ctx, qn_ptr, totals_ptr, sum1_ptr, sum2_ptr, stream),
+                  ctx)
 
 
 def les_profile(ctx, enable):

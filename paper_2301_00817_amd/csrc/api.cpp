@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -13,6 +14,36 @@
 #include "launch.hpp"
 
 using namespace lesjet;
+
+// Device scratch of les_diagnostics_noalloc: the per-block partial sums of
+// the conservation totals (5 per block, at most DIAG_MAX_PARTIALS blocks), in
+// a static array that every GPU the library runs on holds until the process
+// ends.  Host code never passes `scratch` itself (on the host it names a
+// stand-in, not the device array): it takes each device's address once, with
+// that device current, and keeps it in g_scratch_ptr.
+constexpr int DIAG_MAX_PARTIALS = 2048;
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = 5 * (size_t)DIAG_MAX_PARTIALS;   // 80 KiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[MAX_DEVICES];
+
+// The address of `scratch` on the current device `dev` (taken on the first
+// call for that device).
+static hipError_t scratch_address(int dev, double** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 struct les_ctx {
   les_params p;
@@ -35,6 +66,7 @@ struct les_ctx {
   void* R = nullptr;           // residual buffer (storage type)
   void* PT = nullptr;          // point-quantity scratch of the two-pass residual
   double* part = nullptr;      // per-block partial sums of the diagnostics
+  double* part_static = nullptr;   // the same in this device's static scratch (no allocation)
   double* adj = nullptr;       // residual-adjoint scratch (VJP_SCRATCH_VARS variables, FP64)
   double* adj_stage = nullptr; // RK5-step adjoint: stage states 1..4 and one cotangent (25 vars)
   unsigned long long* maxbits = nullptr;
@@ -341,6 +373,10 @@ int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, const d
   c->ph32 = make_phys<float>(p);
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipGetDevice"); }
+  // once per device, with the device current: the address of the static
+  // scratch of the entry points that allocate nothing
+  e = scratch_address(c->device, &c->part_static);
+  if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)"); }
   e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipDeviceGetAttribute"); }
   c->kc = p->precision == LES_FP32_STORAGE ? fused_chunk<float>(c->g, c->num_cu)
@@ -674,6 +710,30 @@ int les_diagnostics(les_ctx* c, const double* Qn, double* totals, double* sum1, 
   else
     e = launch_diagnostics<double>(Qn, (const double*)c->M, c->g, c->ph64, c->part, totals, sum1,
                                    sum2, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics kernels");
+  return LES_OK;
+}
+
+int les_diagnostics_noalloc(les_ctx* c, const double* Qn, double* totals, double* sum1,
+                            double* sum2, void* stream) {
+  int r = ready(c);
+  if (r != LES_OK) return r;
+  if (!Qn) return fail(c, LES_EINVAL, "Qn is NULL");
+  if (!c->part_static) return fail(c, LES_ESTATE, "no static scratch on this device");
+  const size_t need = (size_t)5 * diag_partials(c->g);
+  if (need > NOALLOC_SCRATCH_DOUBLES)
+    return fail(c, LES_EUNSUPPORTED,
+                "the totals need " + std::to_string(need) + " partial sums, beyond the " +
+                    std::to_string(NOALLOC_SCRATCH_DOUBLES) + " of the static scratch");
+  // every partial slot the final reduction reads is written by the partial
+  // pass of the same call first, so nothing needs clearing
+  hipError_t e;
+  if (c->p.precision == LES_FP32_STORAGE)
+    e = launch_diagnostics<float>(Qn, (const float*)c->M, c->g, c->ph64, c->part_static, totals,
+                                  sum1, sum2, (hipStream_t)stream);
+  else
+    e = launch_diagnostics<double>(Qn, (const double*)c->M, c->g, c->ph64, c->part_static, totals,
+                                   sum1, sum2, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "diagnostics kernels");
   return LES_OK;
 }

@@ -184,6 +184,15 @@ __host__ __device__ __forceinline__ T vreman_ratio(const T g[4][3]) {
   return (aa > T(0) && B > T(0)) ? tsqrt(B * trcp(aa)) : T(0);
 }
 
+// 2 S_ij S_ij / 2 = S_ij S_ij with S_ij = (g_ij + g_ji) / 2 (each
+// off-diagonal pair formed once), from g[i][m] = d u_i / d x_m.
+template <typename T>
+__host__ __device__ __forceinline__ T strain_sq(const T g[4][3]) {
+  const T a01 = g[0][1] + g[1][0], a02 = g[0][2] + g[2][0], a12 = g[1][2] + g[2][1];
+  return g[0][0] * g[0][0] + g[1][1] * g[1][1] + g[2][2] * g[2][2] +
+         T(0.5) * (a01 * a01 + a02 * a02 + a12 * a12);
+}
+
 template <typename T>
 struct PointOut {
   T G[3][5];
@@ -237,24 +246,14 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
       const T mu = Tt * a * ph.suth1 * trcp(Tt + ph.suth);    // Sutherland
       T mut = T(0);
       if (ph.sgs == 1) {                                      // Smagorinsky
-        T s2 = T(0);
-        for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) {
-            const T sij = T(0.5) * (g[i][j] + g[j][i]);
-            s2 += sij * sij;
-          }
+        const T s2 = strain_sq(g);
         const T delta = tcbrt(tabs(in.V));
         mut = s.rho * ph.sgs_coef * delta * delta * tsqrt(T(2) * s2);
       } else if (ph.sgs == 2) {                               // Vreman
         const T delta = tcbrt(tabs(in.V));
         mut = s.rho * ph.sgs_coef * delta * delta * vreman_ratio(g);
       } else if (DYN && ph.sgs == 3) {                        // dynamic: C_ds Delta^2 |S|
-        T s2 = T(0);
-        for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) {
-            const T sij = T(0.5) * (g[i][j] + g[j][i]);
-            s2 += sij * sij;
-          }
+        const T s2 = strain_sq(g);
         const T delta = tcbrt(tabs(in.V));
         mut = s.rho * ph.sgs_coef * delta * delta * tsqrt(T(2) * s2);
       }
@@ -269,12 +268,7 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
       // isotropic SGS stress of the dynamic model: sigma_kk / 3 =
       // (2/3) C_I rho Delta^2 |S|^2 acts as a pressure in the momentum and
       // energy point fluxes (stage |S|, coefficient of the launch)
-      T s2 = T(0);
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          const T sij = T(0.5) * (g[i][j] + g[j][i]);
-          s2 += sij * sij;
-        }
+      const T s2 = strain_sq(g);
       const T delta = tcbrt(tabs(in.V));
       const T psgs = ph.iso_coef * s.rho * delta * delta * (T(2) * s2);
       for (int d = 0; d < 3; ++d) {
@@ -284,20 +278,25 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
         out.G[d][4] += psgs * Uc[d];
       }
     }
+    // the viscous coefficient M/Re folded into mu and kappa once: tau and
+    // beta below are C_v tau_ij and C_v beta_j
+    const T mtc = ph.Cv * mt, kapc = ph.Cv * kap;
     const T div = g[0][0] + g[1][1] + g[2][2];
     T tau[3][3];
     for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        tau[i][j] = mt * (g[i][j] + g[j][i] - (i == j ? T(2.0 / 3.0) * div : T(0)));
+      for (int j = i; j < 3; ++j) {
+        tau[i][j] = mtc * (g[i][j] + g[j][i] - (i == j ? T(2.0 / 3.0) * div : T(0)));
+        tau[j][i] = tau[i][j];
+      }
     T beta[3];
     for (int j = 0; j < 3; ++j)
-      beta[j] = tau[0][j] * s.u + tau[1][j] * s.v + tau[2][j] * s.w + kap * g[3][j];
+      beta[j] = tau[0][j] * s.u + tau[1][j] * s.v + tau[2][j] * s.w + kapc * g[3][j];
     for (int d = 0; d < 3; ++d) {
       const T* Sd = in.S[d];
-      out.G[d][1] -= ph.Cv * (Sd[0] * tau[0][0] + Sd[1] * tau[0][1] + Sd[2] * tau[0][2]);
-      out.G[d][2] -= ph.Cv * (Sd[0] * tau[1][0] + Sd[1] * tau[1][1] + Sd[2] * tau[1][2]);
-      out.G[d][3] -= ph.Cv * (Sd[0] * tau[2][0] + Sd[1] * tau[2][1] + Sd[2] * tau[2][2]);
-      out.G[d][4] -= ph.Cv * (Sd[0] * beta[0] + Sd[1] * beta[1] + Sd[2] * beta[2]);
+      out.G[d][1] -= Sd[0] * tau[0][0] + Sd[1] * tau[0][1] + Sd[2] * tau[0][2];
+      out.G[d][2] -= Sd[0] * tau[1][0] + Sd[1] * tau[1][1] + Sd[2] * tau[1][2];
+      out.G[d][3] -= Sd[0] * tau[2][0] + Sd[1] * tau[2][1] + Sd[2] * tau[2][2];
+      out.G[d][4] -= Sd[0] * beta[0] + Sd[1] * beta[1] + Sd[2] * beta[2];
     }
   }
 
@@ -307,12 +306,13 @@ __host__ __device__ inline void point_quantities(const PointIn<T>& in, const Phy
     const T* Sd = in.S[d];
     lam[d] = (tabs(Uc[d]) + a * tsqrt(Sd[0] * Sd[0] + Sd[1] * Sd[1] + Sd[2] * Sd[2])) * aiV;
   }
-  const T s01 = tsqrt(lam[0] * lam[1]);
-  const T s02 = tsqrt(lam[0] * lam[2]);
-  const T s12 = tsqrt(lam[1] * lam[2]);
-  out.lb[0] = lam[0] + s01 + s02;
-  out.lb[1] = lam[1] + s01 + s12;
-  out.lb[2] = lam[2] + s02 + s12;
+  // lambda_d + sqrt(lambda_d lambda_e) + sqrt(lambda_d lambda_f)
+  //   = sqrt(lambda_d) (sqrt(lambda_d) + sqrt(lambda_e) + sqrt(lambda_f))
+  const T r0 = tsqrt(lam[0]), r1 = tsqrt(lam[1]), r2 = tsqrt(lam[2]);
+  const T rs = r0 + r1 + r2;
+  out.lb[0] = r0 * rs;
+  out.lb[1] = r1 * rs;
+  out.lb[2] = r2 * rs;
 
   for (int d = 0; d < 3; ++d) out.nu[d] = in.nu[d];
 }

@@ -52,6 +52,10 @@ VJP_BYTES_PER_POINT = 200
 CSRC = os.path.join(ROOT, "paper_2301_00817_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 DEFAULT_CONFIG = "big1B"
+# The metric this line reports: `value` is the point-update rate; the HBM
+# fraction is `roofline`, FP32 against FP64 `precision_forms`, the adjoint's
+# calls per second `adjoint`.
+METRIC = "Mpoint-RK-stage updates/s + HBM GB/s % of peak, FP32 vs FP64; adjoint VJP/s"
 
 # Algorithmic HBM bytes per interior point and RK stage, the method taken as
 # residual + update: residual reads the stage state (5 values) and the
@@ -335,7 +339,7 @@ def main():
                     r, workload)
 
     out = {
-        "metric": "Mpoint-RK-stage updates/s",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "Mpoint-RK-stage updates/s",
         "n_gpus": 1,

@@ -21,7 +21,6 @@ using namespace lesjet;
 // ends.  Host code never passes `scratch` itself (on the host it names a
 // stand-in, not the device array): it takes each device's address once, with
 // that device current, and keeps it in g_scratch_ptr.
-constexpr int DIAG_MAX_PARTIALS = 2048;
 constexpr size_t NOALLOC_SCRATCH_DOUBLES = 5 * (size_t)DIAG_MAX_PARTIALS;   // 80 KiB
 static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
 

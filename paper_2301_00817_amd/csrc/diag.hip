@@ -84,7 +84,7 @@ __global__ void k_azimuthal_stats(const double* __restrict__ Q, Grid g, Phys<dou
 int diag_partials(const Grid& g) {
   const long long n = (long long)g.nx * g.nr * g.nth;
   long long b = (n + DIAG_BS - 1) / DIAG_BS;
-  return (int)(b > 2048 ? 2048 : (b < 1 ? 1 : b));
+  return (int)(b > DIAG_MAX_PARTIALS ? DIAG_MAX_PARTIALS : (b < 1 ? 1 : b));
 }
 
 template <typename TM>

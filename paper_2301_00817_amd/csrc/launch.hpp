@@ -72,6 +72,9 @@ template <typename T, typename TS>
 hipError_t launch_rk_update(const double* Q0, const T* R, TS* Qout, double* Q64out, const Grid& g,
                             double alpha, const double* dt, hipStream_t s);
 
+// Per-block partial sums of the diagnostics' totals: at most
+// DIAG_MAX_PARTIALS blocks, 5 sums each.
+constexpr int DIAG_MAX_PARTIALS = 2048;
 int diag_partials(const Grid& g);
 
 template <typename TM>

@@ -17,11 +17,13 @@ from oracle import les
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("shape", [(37, 22, 20), (64, 40, 96)])
-def test_product_maps_host_and_device_coordinates_agree(shape):
+@pytest.mark.parametrize("shape,axis_node", [((37, 22, 20), False), ((64, 40, 96), False),
+                                             ((21, 12, 16), True)])
+def test_product_maps_host_and_device_coordinates_agree(shape, axis_node):
+    """Also a mesh whose first radial row lies on the axis (R = 0)."""
     from paper_2301_00817_amd.solver import Solver
-    announce("init forms", shape)
-    pb = problems.jet_problem(*shape, seed=2)
+    announce("init forms", shape, "axis node" if axis_node else "")
+    pb = problems.jet_problem(*shape, seed=2, axis_node=axis_node)
     X, R, TH = pb["grid"]
     prm = pb["params"]
     out = []

@@ -77,7 +77,7 @@ DOMINANT_KERNEL = "k_fused"
 
 # the sources the stage kernel is compiled from and its compiler flags (its
 # traffic record is tied to them)
-STAGE_SOURCES = ("common.hpp", "physics.hpp", "residual_fused.hip")
+STAGE_SOURCES = ("common.hpp", "physics.hpp", "plane_io.hpp", "residual_fused.hip")
 
 
 def source_hash():

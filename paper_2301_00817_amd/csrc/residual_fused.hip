@@ -25,6 +25,7 @@
 // the new state for the next step's dt.
 #include "launch.hpp"
 #include "physics.hpp"
+#include "plane_io.hpp"
 
 namespace lesjet {
 
@@ -40,25 +41,29 @@ constexpr int NPQ = 8;                // G(5), lambda_bar, nu, V per direction
 
 enum { EPI_R = 0, EPI_RK = 1, EPI_RK_LAST = 2 };
 
+// Global memory is addressed plane by plane (plane_io.hpp): one 32-bit
+// offset register per column serves every variable and plane of the march.
+
+// Byte offset of a column a thread reads: outside the padded box the nearest
+// point of it (finite data that no output uses; clamping instead of a
+// default value spares the moves that would set the default before every
+// load).
 template <typename T>
-__device__ __forceinline__ void load_q(const T* __restrict__ Q, const Grid& g, int i, int j, int k,
-                                       T q[5]) {
-  // outside the padded box the nearest point of it is read: a finite state
-  // that no output uses (clamping instead of a default value spares the
-  // moves that would set the default before every load)
-  const int o = g.at(min(max(i, -NG), g.nx + NG - 1), min(max(j, -NG), g.nr + NG - 1), k);
-#pragma unroll
-  for (int c = 0; c < 5; ++c) q[c] = Q[(long long)c * g.vs + o];
+__device__ __forceinline__ unsigned q_col(const Grid& g, int i, int j) {
+  return col_off<T>(g, min(max(i, -NG), g.nx + NG - 1), min(max(j, -NG), g.nr + NG - 1));
 }
 
 template <typename T>
-__device__ __forceinline__ void load_metrics(const T* __restrict__ M, const Grid& g, int i, int j,
-                                             int k, T m[10]) {
-  // columns beyond [-1, n] (no output needs them) read the nearest column of
-  // that range: finite metrics, no default values to set
-  const int o = g.at(min(max(i, -1), g.nx), min(max(j, -1), g.nr), k);
+__device__ __forceinline__ void load_q(const T* Q, const Grid& g, unsigned col, int k, T q[5]) {
 #pragma unroll
-  for (int c = 0; c < 10; ++c) m[c] = M[(long long)c * g.vs + o];
+  for (int c = 0; c < 5; ++c) q[c] = gld(Q, g, c, k, col);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_metrics(const T* M, const Grid& g, unsigned col, int k,
+                                             T m[10]) {
+#pragma unroll
+  for (int c = 0; c < 10; ++c) m[c] = gld(M, g, c, k, col);
 }
 
 // Workgroups are dealt to the eight XCDs (each with its own L2) in turn.  The
@@ -156,6 +161,14 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   else if (tid < 2 * FR_X) { bry = FR_Y - 1; brx = tid - FR_X; }
   else { const int r = tid - 2 * FR_X; bry = 1 + (r >> 1); brx = (r & 1) ? FR_X - 1 : 0; }
   const int bi = i0 - 2 + brx, bj = j0 - 2 + bry;
+  // Byte offsets within a plane of the own column and of the border point.
+  // Every column that produces or feeds an output lies in the padded box,
+  // where the clamp is the identity, so oq is also the offset of the output
+  // point; the columns beyond [-1, n] read metrics and held viscosities of
+  // ghost columns, whose point quantities no face uses.  oq64: the same
+  // column in the FP64 arrays (Q^(0), Q^(n+1)).
+  const unsigned oq = q_col<T>(g, i, j), oob = q_col<T>(g, bi, bj);
+  const unsigned oq64 = sizeof(T) == 8 ? oq : 2u * oq;
 
   const bool axis_row = AXIS && j == 0;      // centerline row (not advanced)
   const bool axis_face = AXIS && j == 1;     // face j - 1/2 is the axis face
@@ -179,9 +192,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   auto load_lag = [&](int kk, T v[2]) {
     // columns beyond [-1, n] read the nearest held column (all of [-1, n]^3
     // is written at stage 1); no output uses them
-    const int o = g.at(min(max(i, -1), g.nx), min(max(j, -1), g.nr), kk);
-    v[0] = visc[o];
-    v[1] = visc[(long long)g.vs + o];
+    v[0] = gld(visc, g, 0, kk, oq);
+    v[1] = gld(visc, g, 1, kk, oq);
   };
   // zeta-face state of plane kk-1 (interior columns)
   T Gz[5], lbz = 0, nuz = 0, Vz = 0;
@@ -191,21 +203,21 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
 
   {
     T q[5], pc[5];
-    load_q(Qin, g, i, j, k0 - 2, q);
+    load_q(Qin, g, oq, k0 - 2, q);
     prim5(q, ph, Pb);                    // primitives at kk-1 = k0-2
 #pragma unroll
     for (int c = 0; c < 5; ++c) Wa[c] = q[c];
     Wa[4] += Pb[4];
-    load_q(Qin, g, i, j, k0 - 1, q);     // plane kk = k0-1 of the own column
+    load_q(Qin, g, oq, k0 - 1, q);       // plane kk = k0-1 of the own column
     prim5(q, ph, pc);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       sQ[c][ty + 1][tx + 1] = q[c];
       sP[c][ty + 1][tx + 1] = pc[c];
     }
-    load_q(Qin, g, i, j, k0, Qd);
+    load_q(Qin, g, oq, k0, Qd);
     prim5(Qd, ph, Pd);
-    load_metrics(M, g, i, j, k0 - 1, met);
+    load_metrics(M, g, oq, k0 - 1, met);
     if (LAG == LAG_READ) load_lag(k0 - 1, lag);
   }
 #pragma unroll
@@ -213,7 +225,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
 
   if (has_b) {                           // border of the first plane
     T bq[5], bp[5];
-    load_q(Qin, g, bi, bj, k0 - 1, bq);
+    load_q(Qin, g, oob, k0 - 1, bq);
     prim5(bq, ph, bp);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
@@ -226,14 +238,13 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     const bool more = kk < k1;
     // own-column and metric loads of the next plane, in flight during (b)
     if (more) {
-      if (kk + 2 <= k1 + 1) load_q(Qin, g, i, j, kk + 2, Qn);
-      load_metrics(M, g, i, j, kk + 1, metn);
+      if (kk + 2 <= k1 + 1) load_q(Qin, g, oq, kk + 2, Qn);
+      load_metrics(M, g, oq, kk + 1, metn);
       if (LAG == LAG_READ) load_lag(kk + 1, lagn);
     }
     if (PQ0 && interior && kk - 1 >= k0) {
-      const int o = g.at(i, j, kk - 1);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) q0p[c] = Q0[(long long)c * g.vs + o];
+      for (int c = 0; c < 5; ++c) q0p[c] = gld(Q0, g, c, kk - 1, oq64);
     }
     // (a) plane kk is in LDS (written before the loop or at the end of the
     // previous iteration)
@@ -265,9 +276,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     if (LAG == LAG_READ) { in.mt = lag[0]; in.kap = lag[1]; }
     point_quantities<T, LAG, DYN>(in, ph, po);
     if (LAG == LAG_WRITE && col_ok && ph.viscous) {
-      const int o = g.at(i, j, kk);
-      visc[o] = po.mt;
-      visc[(long long)g.vs + o] = po.kap;
+      gst(visc, g, 0, kk, oq, po.mt);
+      gst(visc, g, 1, kk, oq, po.kap);
     }
     if (AXIS && axis_row) {
       // centerline through the nodes: S^eta = 0 on the axis, so the eta
@@ -288,7 +298,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     sE[7][ty][tx] = in.V;
     // border of the next plane, in flight during the face phase
     T Bn[5];
-    if (more && has_b) load_q(Qin, g, bi, bj, kk + 1, Bn);
+    if (more && has_b) load_q(Qin, g, oob, kk + 1, Bn);
     __syncthreads();
 
     // (c) faces
@@ -329,6 +339,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     }
     __syncthreads();
     if (interior && kk >= k0) {
+      const bool emit = kk - 1 >= k0;       // R at (i, j, kk-1) completes here
       // flux differences of the in-plane faces (output planes only)
       T rhs[5] = {0, 0, 0, 0, 0};
       if (kk < k1) {
@@ -343,32 +354,39 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
       Wc[4] += sP[4][ty + 1][tx + 1];
       Wd[4] += Pd[4];
       face_flux(Gz, po.G[2], lbz, po.lb[2], nuz, po.nu[2], Vz, in.V, Wa, Wb, Wc, Wd, false, ph, Fk);
-      if (kk - 1 >= k0) {
-        // R at (i, j, kk-1) is complete
-        const int o = g.at(i, j, kk - 1);
+      if (emit) {
+        // the epilogue's loads ahead of its stores (the compiler cannot order
+        // buffer accesses of different arrays by itself): Q^(0) of the output
+        // point (loaded an iteration ahead where registers allow) and, at the
+        // last stage, its metrics (cached in L2) for the next step's dt
+        double q0[5], S[3][3];
+        if (EPI != EPI_R) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) q0[c] = PQ0 ? q0p[c] : gld(Q0, g, c, kk - 1, oq64);
+        }
+        if (EPI == EPI_RK_LAST) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S[d][c] = (double)gld(M, g, 3 * d + c, kk - 1, oq);
+        }
         const T iV = trcp(Vz);
         T R[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) R[c] = AXIS && axis_row ? T(0) : (acc[c] + Fk[c]) * iV;
         if (EPI == EPI_R) {
 #pragma unroll
-          for (int c = 0; c < 5; ++c) out[(long long)c * g.vs + o] = R[c];
+          for (int c = 0; c < 5; ++c) gst(out, g, c, kk - 1, oq, R[c]);
         } else {
           const double ad = PQ0 ? ad_pre : alpha * (*dtp);
           double qn[5];
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
-            const long long oc = (long long)c * g.vs + o;
-            qn[c] = (PQ0 ? q0p[c] : Q0[oc]) - ad * (double)R[c];
-            out[oc] = (T)qn[c];
-            if (EPI == EPI_RK_LAST && Q64) Q64[oc] = qn[c];
+            qn[c] = q0[c] - ad * (double)R[c];
+            gst(out, g, c, kk - 1, oq, (T)qn[c]);
+            if (EPI == EPI_RK_LAST && Q64) gst(Q64, g, c, kk - 1, oq64, qn[c]);
           }
           if (EPI == EPI_RK_LAST) {
-            double S[3][3];   // metrics of the output point (cached in L2)
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-              for (int c = 0; c < 3; ++c) S[d][c] = (double)M[(long long)(3 * d + c) * g.vs + o];
             const double x = lambda_sum(qn, S, (double)Vz, ph64);
             if (!(AXIS && axis_row) && (x != x || x > lmax)) lmax = x;
           }

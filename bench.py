@@ -77,7 +77,8 @@ DOMINANT_KERNEL = "k_fused"
 
 # the sources the stage kernel is compiled from and its compiler flags (its
 # traffic record is tied to them)
-STAGE_SOURCES = ("common.hpp", "physics.hpp", "plane_io.hpp", "residual_fused.hip")
+STAGE_SOURCES = ("common.hpp", "physics.hpp", "plane_io.hpp", "fused_stage.hpp",
+                 "residual_fused.hip", "residual_fused32.hip")
 
 
 def source_hash():
@@ -86,7 +87,9 @@ def source_hash():
     for f in STAGE_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + fh.read())
-    flags = list(build.CFLAGS) + list(build.SOURCE_FLAGS.get("residual_fused.hip", []))
+    flags = list(build.CFLAGS)
+    for f in STAGE_SOURCES:
+        flags += list(build.SOURCE_FLAGS.get(f, []))
     h.update(" ".join(f for f in flags if not f.startswith("/")).encode())
     return h.hexdigest()[:16]
 

@@ -334,9 +334,12 @@ __host__ __device__ __forceinline__ void face_flux(const T GL[5], const T GR[5],
   const T e4 = tmax(T(0), ph.k4 - e2);
   const T lf = T(0.5) * (lbL + lbR);
   const T Vf = physical ? T(0) : T(0.5) * (VL + VR);
+  // V_f d = a2 (W_R - W_L) - a4 ((W_{R+1} - W_{L-1}) - 3 (W_R - W_L))
+  const T vl = Vf * lf, a2 = vl * e2, a4 = vl * e4;
   for (int c = 0; c < 5; ++c) {
-    const T dis = lf * (e2 * (WR[c] - WL[c]) - e4 * (Wp[c] - T(3) * WR[c] + T(3) * WL[c] - Wm[c]));
-    F[c] = T(0.5) * (GL[c] + GR[c]) - Vf * dis;
+    const T A = WR[c] - WL[c];
+    const T B = (Wp[c] - Wm[c]) - T(3) * A;
+    F[c] = T(0.5) * (GL[c] + GR[c]) - a2 * A + a4 * B;
   }
 }
 

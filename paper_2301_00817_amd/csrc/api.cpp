@@ -198,6 +198,9 @@ static int make_layout(const les_params* p, Grid& g, CGrid& cg, std::string& why
     why = "one padded variable exceeds 2^31 - 1 elements";
     return LES_EUNSUPPORTED;
   }
+  // With at least nine planes per variable (nth >= 5) a plane of FP64 data
+  // then stays below 2^31 bytes: the byte range of the stage kernel's
+  // per-plane buffer resources.
   g.nx = p->nx; g.nr = p->nr; g.nth = p->nth;
   g.pitch = (int)pitch; g.plane = (int)plane; g.vs = (int)vs;
   cg.nx = p->nx; cg.nr = p->nr; cg.nth = p->nth;

@@ -109,13 +109,16 @@ def test_init_grid_rejects_bad_mesh_arguments_before_device_work():
 
 def test_big_mesh_layout_fits_32bit_offsets():
     """The 1250 x 640 x 1250 mesh: one padded variable stays below 2^31
-    elements, so per-variable offsets are 32-bit."""
+    elements, so per-variable offsets are 32-bit, and one plane of FP64 data
+    below 2^31 bytes (the range of the stage kernel's per-plane buffer
+    resources)."""
     from paper_2301_00817_amd import binding as B
     p = _params()
     p.nx, p.nr, p.nth = 1250, 640, 1250
     pitch, dims, vs = B.les_layout(p)
     assert vs < 2 ** 31
     assert 5 * vs > 2 ** 32          # whole fields need 64-bit bases
+    assert dims[1] * pitch * 8 < 2 ** 31
 
 
 @pytest.mark.parametrize("call", [

@@ -26,6 +26,9 @@ The JSON line also carries
                measured by rocprofv3 FETCH_SIZE + WRITE_SIZE
                (profiles/traffic.json) when those counters were taken on the
                current kernel sources and on this workload, else null;
+               `stream_GBs` the rate of a plain elementwise streaming kernel
+               (4 GiB read and written) measured in the same run, the
+               achievable bandwidth beside the nominal peak;
   cpu_baseline the CPU oracle (plain NumPy FP64, one thread) on bounded
                samples: one residual and one RK5 step of the 160 x 100 x 128
                and 288 x 160 x 128 jet meshes, median of three runs each;
@@ -218,10 +221,11 @@ def copy_probe(gib, dev, reps=5):
     e1.record(st)
     torch.cuda.synchronize()
     ms2 = e0.elapsed_time(e1) / reps
-    print(json.dumps({"copy_probe": {"bytes_read": n * 8, "bytes_written": n * 8,
-                                     "copy_ms": ms, "copy_GBps": 2 * n * 8 / ms / 1e6,
-                                     "elementwise_ms": ms2,
-                                     "elementwise_GBps": 2 * n * 8 / ms2 / 1e6}}), flush=True)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_read": n * 8, "bytes_written": n * 8, "copy_ms": ms,
+            "copy_GBps": 2 * n * 8 / ms / 1e6, "elementwise_ms": ms2,
+            "elementwise_GBps": 2 * n * 8 / ms2 / 1e6}
 
 
 def rocprof_summary(csv_dir, out_path, command, kernel=DOMINANT_KERNEL):
@@ -325,7 +329,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.copy_probe:
-        copy_probe(args.copy_probe, dev)
+        print(json.dumps({"copy_probe": copy_probe(args.copy_probe, dev)}), flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": time_adjoint("adj2M", dev)}), flush=True)
@@ -386,6 +390,14 @@ def main():
                                           "roofline": roof2}}
         print("[bench] adjoint timing", file=sys.stderr, flush=True)
         out["adjoint"] = time_adjoint("adj2M", dev)
+        # the achievable streaming rate on this machine: a plain elementwise
+        # kernel reading and writing 4 GiB, beside the nominal 8 TB/s peak
+        print("[bench] streaming probe", file=sys.stderr, flush=True)
+        cp = copy_probe(4, dev)
+        stream = round(cp["elementwise_GBps"], 1)
+        for rf in (out["roofline"], out["precision_forms"][other + "_run"]["roofline"]):
+            rf["stream_GBs"] = stream
+            rf["frac_of_stream"] = round(rf["achieved"] / stream, 4)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

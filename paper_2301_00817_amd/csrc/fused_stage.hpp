@@ -93,7 +93,7 @@ template <typename T> struct PrefetchQ0 { static constexpr bool on = sizeof(T) =
 // gains nothing from it.
 template <typename T> struct WavePrio { static constexpr bool on = sizeof(T) == 8; };
 
-// Register budget: FP64 two waves per SIMD (242 VGPRs), FP32 four (128).
+// Register budget: FP64 two waves per SIMD (up to 256 VGPRs), FP32 four (128).
 template <typename T> struct FusedOcc;
 template <> struct FusedOcc<double> { static constexpr int waves = 2; };
 template <> struct FusedOcc<float> { static constexpr int waves = 4; };

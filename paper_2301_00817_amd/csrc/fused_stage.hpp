@@ -460,7 +460,11 @@ int fused_chunk(const Grid& g, int num_cu) {
   constexpr int FT_X = Tile<T>::X - 2, FT_Y = Tile<T>::Y - 2;
   num_cu *= Tile<T>::PER_CU;          // resident blocks
   const long long tiles = (long long)((g.nx + FT_X - 1) / FT_X) * ((g.nr + FT_Y - 1) / FT_Y);
-  // pick the chunk length that minimises (rounds of resident blocks) x (planes per block).
+  // pick the chunk length that minimises (rounds of resident blocks) x (planes per block),
+  // over every length from 4 planes to the cap (lengths that divide the
+  // azimuth leave no short last chunk: against powers of two only, 5.6 % on
+  // the 128 x 128 x 360 mesh and 3.1 % on 1700 x 1700 x 360 in FP64, 1.4-1.6 %
+  // in FP32, 0.5 % on 1250 x 640 x 1250).
   // FP32 (four blocks per CU) stops at 16 planes: longer chunks measured
   // slower on large meshes (4 % at 1e8 points, 8 % at 1e9), the resident
   // blocks of a round drifting apart in k and sharing fewer halo lines in
@@ -472,7 +476,7 @@ int fused_chunk(const Grid& g, int num_cu) {
     int best = g.nth;
     long long best_rounds = 0;
     double best_cost = 1e300;
-    for (int kc = 4; kc <= kc_max; kc *= 2) {
+    for (int kc = 4; kc <= kc_max; ++kc) {
       const long long nb = tiles * ((g.nth + kc - 1) / kc);
       const long long rounds = (nb + num_cu - 1) / num_cu;
       const double cost = (double)rounds * (kc + 2);

@@ -39,6 +39,10 @@ CFLAGS = [
 # faster than with the ILP scheduling, which spills).
 SOURCE_FLAGS = {"residual_fused.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
+# Host-side ranges around the API calls and RK stages for rocprofv3
+# --marker-trace (ROCTx; inert when no tool is attached).
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+
 
 def _hipcc():
     for c in ("/opt/rocm/bin/hipcc", shutil.which("hipcc")):
@@ -104,7 +108,7 @@ def build(verbose=False):
                 print(err, file=sys.stderr)
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-Wl,--no-undefined", "-o", tmp,
-           *objs]
+           *objs, *LIBS]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")

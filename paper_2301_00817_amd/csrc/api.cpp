@@ -8,6 +8,8 @@
 #include <mutex>
 #include <new>
 #include <string>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <vector>
 
 #include "lesjet.h"
@@ -99,6 +101,16 @@ static long prof_begin(les_ctx* c, hipStream_t s) {
 static void prof_end(les_ctx* c, long k, hipStream_t s) {
   if (k >= 0) (void)hipEventRecord(c->ev[2 * k + 1], s);
 }
+
+// Host-side range (ROCTx) around an API call or an RK stage, for
+// rocprofv3 --marker-trace: it spans the enqueueing of the call's kernels
+// on the host timeline (inert when no tool is attached).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 static thread_local std::string t_err;
 
@@ -353,6 +365,7 @@ static int product_table(const les_params* p, const double* X, const double* R, 
 
 int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, const double* X,
                   const double* R, const double* TH, void* stream) {
+  const Range range("les_init_grid");
   if (!out) return fail(nullptr, LES_EINVAL, "out is NULL");
   *out = nullptr;
   std::string why;
@@ -416,6 +429,7 @@ int les_init_grid(les_ctx** out, const les_params* p, const double* xyz, const d
 }
 
 int les_metrics(les_ctx* c, double* metrics_out, void* stream) {
+  const Range range("les_metrics");
   if (!c) return fail(nullptr, LES_EINVAL, "ctx is NULL");
   if (c->metrics_done) return fail(c, LES_ESTATE, "metrics already computed");
   if (!c->coords) return fail(c, LES_ESTATE, "no coordinates");
@@ -597,6 +611,7 @@ int les_residual_reference(les_ctx* c, void* Q, void* R, void* stream) {
 }
 
 int les_residual(les_ctx* c, void* Q, void* R, void* stream) {
+  const Range range("les_residual");
   int r = ready(c);
   if (r != LES_OK) return r;
   if (!Q || !R) return fail(c, LES_EINVAL, "Q or R is NULL");
@@ -645,6 +660,10 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
     T* const held = cur;
     T* src = cur;
     for (int l = 0; l < 5 && e == hipSuccess; ++l) {
+      static const char* const stage_name[5] = {"lesjet RK stage 1", "lesjet RK stage 2",
+                                                "lesjet RK stage 3", "lesjet RK stage 4",
+                                                "lesjet RK stage 5"};
+      const Range rs(stage_name[l]);
       e = l > 0 && held_sched ? ghosts_held<T>(c, src, held, s) : ghosts<T>(c, src, s);
       // dynamic model: coefficients of this stage's state (held: of Q^n)
       if (e == hipSuccess && dynamic_model(c) && (l == 0 || !held_sched))
@@ -685,6 +704,7 @@ static int rk5_steps(les_ctx* c, double* Qn, int nsteps, double dt_fixed, double
 
 int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed, double* dt_out,
                  void* stream) {
+  const Range range("les_rk5_step");
   int r = ready(c);
   if (r != LES_OK) return r;
   if (!Qn) return fail(c, LES_EINVAL, "Qn is NULL");
@@ -698,6 +718,7 @@ int les_rk5_step(les_ctx* c, double* Qn, int32_t nsteps, double dt_fixed, double
 
 int les_diagnostics(les_ctx* c, const double* Qn, double* totals, double* sum1, double* sum2,
                     void* stream) {
+  const Range range("les_diagnostics");
   int r = ready(c);
   if (r != LES_OK) return r;
   if (!Qn) return fail(c, LES_EINVAL, "Qn is NULL");
@@ -776,6 +797,7 @@ static int step_adjoint_ready(les_ctx* c) {
 
 int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, double* inflow_bar,
                      void* stream) {
+  const Range range("les_residual_vjp");
   int r = adjoint_ready(c);
   if (r != LES_OK) return r;
   if (!Q || !Rbar || !Qbar) return fail(c, LES_EINVAL, "Q, Rbar or Qbar is NULL");
@@ -785,6 +807,7 @@ int les_residual_vjp(les_ctx* c, double* Q, const double* Rbar, double* Qbar, do
 
 int les_rk5_step_vjp(les_ctx* c, double* Qn, double dt, const double* Qbar_np1, double* Qbar_n,
                      double* inflow_bar, void* stream) {
+  const Range range("les_rk5_step_vjp");
   int r = step_adjoint_ready(c);
   if (r != LES_OK) return r;
   if (!Qn || !Qbar_np1 || !Qbar_n) return fail(c, LES_EINVAL, "Qn, Qbar_np1 or Qbar_n is NULL");

@@ -28,27 +28,31 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* A, const G
       g.plane * (int)sizeof(T), RSRC_DW3);
 }
 
-__device__ __forceinline__ float buf_ld(float*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
-__device__ __forceinline__ double buf_ld(double*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
 
 // load / store variable c of plane k at byte offset `off` within the plane
 template <typename T>
 __device__ __forceinline__ T gld(const T* A, const Grid& g, int c, int k, unsigned off) {
-  return buf_ld((T*)nullptr, plane_rsrc(A, g, c, k), off);
+  return buf_ld<T>(plane_rsrc(A, g, c, k), off);
 }
 template <typename T>
 __device__ __forceinline__ void gst(T* A, const Grid& g, int c, int k, unsigned off, T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit elements");
   const __amdgpu_buffer_rsrc_t r = plane_rsrc(A, g, c, k);
-  if (sizeof(T) == 4)
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)v), r, (int)off, 0, 0);
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
   else
     __builtin_amdgcn_raw_buffer_store_b64(
-        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, (double)v), r, (int)off, 0,
-        0);
+        __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, (int)off, 0, 0);
 }
 
 // byte offset of column (i, j) within a plane of a padded array of T

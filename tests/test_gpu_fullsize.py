@@ -1,6 +1,8 @@
 """Parity at the measured sizes, in the configuration bench.py times (the
 same workload generator — the mesh built by the library from its 1-D maps —
-precision and launch shapes), on sampled outputs.
+precision and launch shapes), on sampled outputs: the 288 x 160 x 128 jet,
+the paper's mesh A shape 128 x 128 x 360 (no SGS model, as in the paper's
+runs; 24-plane FP64 chunks) and the 1250 x 640 x 1250 jet.
 
 The residual at an interior point depends only on the state and coordinates
 within two points of it (point quantities at the neighbours need their
@@ -102,6 +104,8 @@ def _oracle_at(prm, xyz_b, Q_b, h):
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("config,precision,nsamp", [("jet5.9M", "fp64", 48),
                                                     ("jet5.9M", "fp32", 48),
+                                                    ("meshA", "fp64", 32),
+                                                    ("meshA", "fp32", 32),
                                                     ("big1B", "fp64", 24),
                                                     ("big1B", "fp32", 24)])
 def test_sampled_residual(config, precision, nsamp):
@@ -145,8 +149,8 @@ def test_sampled_residual(config, precision, nsamp):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("config,precision,nsamp", [("jet5.9M", "fp64", 4), ("big1B", "fp64", 3),
-                                                    ("big1B", "fp32", 3)])
+@pytest.mark.parametrize("config,precision,nsamp", [("jet5.9M", "fp64", 4), ("meshA", "fp64", 3),
+                                                    ("big1B", "fp64", 3), ("big1B", "fp32", 3)])
 def test_sampled_rk5_step(config, precision, nsamp):
     """One CFL step of the workload bench.py times (its stage-kernel
     instances, chunking and launch shapes); the state at sampled points

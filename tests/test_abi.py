@@ -165,3 +165,69 @@ def test_validate_accepts_both_schedules_and_rejects_others():
     with pytest.raises(B.LesError) as e:
         B.les_validate(_params(schedule=5))
     assert e.value.code == B.LES_EINVAL
+
+
+C_CLIENT = r"""
+#include <stdio.h>
+#include <string.h>
+#include "lesjet.h"
+
+/* a C99 client of the host-only entry points: the header is plain C */
+int main(void) {
+  les_params p;
+  int64_t pitch = 0, dims[3] = {0, 0, 0}, vs = 0;
+  size_t bytes = 0;
+  int i;
+  memset(&p, 0, sizeof p);
+  p.nx = 1250; p.nr = 640; p.nth = 1250;
+  p.bc[0] = LES_BC_INFLOW; p.bc[1] = LES_BC_OUTFLOW; p.bc[2] = LES_BC_AXIS;
+  p.bc[3] = LES_BC_FARFIELD; p.bc[4] = LES_BC_PERIODIC; p.bc[5] = LES_BC_PERIODIC;
+  p.gamma = 1.4; p.Pr = 0.72; p.Pr_sgs = 0.9; p.visc_coef = 1.4 / 1.5e6;
+  p.suth_S = 110.4 / 288.15; p.Cs = 0.148; p.k2 = 0.25; p.k4 = 0.016; p.cfl = 0.5;
+  p.rk_alpha[0] = 0.25; p.rk_alpha[1] = 1.0 / 6.0; p.rk_alpha[2] = 0.375;
+  p.rk_alpha[3] = 0.5; p.rk_alpha[4] = 1.0;
+  p.ref_prim[0] = 1.0; p.ref_prim[1] = 0.05; p.ref_prim[4] = 1.0 / 1.4;
+  p.p_exit = 1.0 / 1.4;
+  p.sgs_model = LES_SGS_SMAGORINSKY; p.precision = LES_FP64; p.schedule = LES_SCHEDULE_STAGE;
+  if (les_validate(&p) != LES_OK) return 10;
+  if (les_layout(&p, &pitch, dims, &vs) != LES_OK) return 11;
+  if (les_device_bytes(&p, &bytes) != LES_OK) return 12;
+  printf("%lld %lld %lld %lld %lld %zu\n", (long long)pitch, (long long)dims[0],
+         (long long)dims[1], (long long)dims[2], (long long)vs, bytes);
+  p.nx = 4;                                        /* below the minimum size */
+  if (les_validate(&p) != LES_EINVAL) return 13;
+  for (i = 0; i < 6; ++i) p.bc[i] = LES_BC_PERIODIC;
+  p.nx = 16; p.precision = 7;                      /* unknown precision */
+  if (les_validate(&p) != LES_EINVAL) return 14;
+  return 0;
+}
+"""
+
+
+def test_header_is_c99_and_a_c_client_links(tmp_path):
+    """include/lesjet.h compiles as strict C99 with warnings as errors, and a
+    C program linked against the library gets from the host-only entry
+    points the layout the Python binding reports (no GPU touched)."""
+    import shutil
+    import subprocess
+    from paper_2301_00817_amd import binding as B
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "client.c"
+    src.write_text(C_CLIENT)
+    exe = tmp_path / "client"
+    lib_dir = os.path.dirname(B.LIB_PATH)
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                        "-L", lib_dir, "-llesjet", f"-Wl,-rpath,{lib_dir}"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    pitch, d0, d1, d2, vs, nbytes = (int(x) for x in r.stdout.split())
+    p = _params()
+    p.nx, p.nr, p.nth = 1250, 640, 1250
+    pitch_py, dims_py, vs_py = B.les_layout(p)
+    assert (pitch, (d0, d1, d2), vs) == (pitch_py, tuple(dims_py), vs_py)
+    assert nbytes > 10 * 8 * vs            # at least the ten FP64 metric variables

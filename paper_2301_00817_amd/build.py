@@ -95,6 +95,28 @@ def build_device_checks():
     return DEVCHECKS_LIB
 
 
+CCLIENT_SRC = os.path.join(ROOT, "tests", "c_client.c")
+CCLIENT_EXE = os.path.join(LIBDIR, "c_client")
+
+
+def build_c_client():
+    """Plain C client of the library (GPU test helper): C99, no C++, linked
+    against liblesjet.so and the HIP runtime."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        return None
+    tmp = CCLIENT_EXE + ".tmp"
+    cmd = [cc, "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include", CCLIENT_SRC, "-o", tmp,
+           "-L", LIBDIR, "-llesjet", f"-Wl,-rpath,{LIBDIR}", "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C client build failed:\n{r.stderr[-6000:]}")
+    os.replace(tmp, CCLIENT_EXE)
+    return CCLIENT_EXE
+
+
 def build(verbose=False):
     """Compile all sources, link the library and the test check libraries."""
     os.makedirs(BUILD, exist_ok=True)
@@ -117,6 +139,8 @@ def build(verbose=False):
         build_checks()
     if os.path.exists(DEVCHECKS_SRC):
         build_device_checks()
+    if os.path.exists(CCLIENT_SRC):
+        build_c_client()
     return LIB
 
 

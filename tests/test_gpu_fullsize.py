@@ -24,8 +24,8 @@ import numpy as np
 import pytest
 import torch
 
-from _helpers import announce, report
-from cases import mesh
+from _helpers import announce, make_solver, report
+from cases import mesh, problems
 from oracle import les
 
 pytestmark = pytest.mark.gpu
@@ -203,4 +203,32 @@ def test_sampled_rk5_step(config, precision, nsamp):
         assert inc.max() <= 1e-3          # the FP32-form residual's bar
     s.close()
     del Qn, Qi, Q1
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-13), ("fp32", 1e-9)])
+def test_periodic_box_conserves_at_scale(precision, bar):
+    """A property of every point at a size the oracle cannot run: on the
+    periodic 384^3 box (56.6 M points, many rounds of tiles and k-chunks)
+    each face flux enters its two cells with opposite signs, across tiles,
+    chunks and the periodic seams, so the totals of J^-1 Q stay constant
+    over RK5 steps.  Bars: the rounding of the residual's flux differences
+    summed over the box, 1e-13 of the totals in FP64; in the FP32-storage
+    form the residual is rounded to FP32 per point (about 1e-7 of the flux
+    scale), a random walk over 5.7e7 points that stays far below 1e-9."""
+    announce("box-conservation", 384, precision)
+    pb = problems.box_problem(384)
+    s = make_solver(pb, precision=precision)
+    Qn = s.pad(pb["Q"].cuda(), dtype=torch.float64)
+    del pb
+    t0 = s.diagnostics(Qn).cpu().numpy()
+    s.rk5_step(Qn, 2)
+    t1 = s.diagnostics(Qn).cpu().numpy()
+    assert np.isfinite(t1).all()
+    drift = [abs(t1[c] - t0[c]) / max(abs(t0[c]), abs(t0[1])) for c in range(5)]
+    report(f"box384 {precision} conservation over 2 steps", relative_drift=np.array(drift))
+    assert max(drift) <= bar
+    s.close()
+    del Qn
     torch.cuda.empty_cache()

@@ -83,6 +83,15 @@ struct TileMap {
 // of the output point an iteration ahead (FP32 at 128 VGPRs does not).
 template <typename T> struct PrefetchQ0 { static constexpr bool on = sizeof(T) == 8; };
 
+// The last stage of a step evaluates the next step's CFL sum at its output
+// point, which needs that point's metric terms, loaded two planes earlier
+// and no longer in L2 (a reload there cost the FP64 kernel 10 ms, a sixth
+// of the stage, on 1e9 points).  The FP64 kernel carries them from the
+// previous plane in registers instead, freed in that stage by loading Q^(0)
+// and the next plane's border where they are used rather than ahead; the
+// FP32 kernel has no registers for them (it spills) and reloads.
+template <typename T> struct CarryS { static constexpr bool on = sizeof(T) == 8; };
+
 // Wave priority: the FP64 kernel (two waves per SIMD, bound by latency)
 // raises its waves' issue priority from the face phase to the end of the
 // epilogue, so that a wave that has its plane in LDS finishes the plane and
@@ -188,7 +197,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   T Qn[5];               // Q at kk+2, in flight
   T met[10], metn[10];   // metrics at (i, j, kk) and the prefetch for kk+1
   T lag[2], lagn[2];     // held (mu + mu_sgs, conductivity), same planes (LAG_READ)
-  constexpr bool PQ0 = EPI != EPI_R && PrefetchQ0<T>::on;
+  constexpr bool CS = EPI == EPI_RK_LAST && CarryS<T>::on;
+  constexpr bool PQ0 = EPI != EPI_R && !CS && PrefetchQ0<T>::on;
   double q0p[5];         // Q^(0) at (i, j, kk-1), loaded at the top of iteration kk
   const double ad_pre = PQ0 ? alpha * (*dtp) : 0.0;
   auto load_lag = [&](int kk, T v[2]) {
@@ -202,6 +212,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   T acc[5];              // RHS at kk-1 without its zeta face kk-1/2:
                          // in-plane faces minus the zeta face kk-3/2
   double lmax = 0.0;
+  T Sp[9];               // last stage (CS): metric terms of plane kk-1
 
   {
     T q[5], pc[5];
@@ -300,7 +311,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     sE[7][ty][tx] = in.V;
     // border of the next plane, in flight during the face phase
     T Bn[5];
-    if (more && has_b) load_q(Qin, g, oob, kk + 1, Bn);
+    if (!CS && more && has_b) load_q(Qin, g, oob, kk + 1, Bn);
     __syncthreads();
 
     // (c) faces
@@ -360,7 +371,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
         // the epilogue's loads ahead of its stores (the compiler cannot order
         // buffer accesses of different arrays by itself): Q^(0) of the output
         // point (loaded an iteration ahead where registers allow) and, at the
-        // last stage, its metrics (cached in L2) for the next step's dt
+        // last stage, its metric terms for the next step's dt (carried in
+        // registers in FP64, reloaded in FP32)
         double q0[5], S[3][3];
         if (EPI != EPI_R) {
 #pragma unroll
@@ -370,7 +382,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
 #pragma unroll
           for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) S[d][c] = (double)gld(M, g, 3 * d + c, kk - 1, oq);
+            for (int c = 0; c < 3; ++c)
+              S[d][c] = CS ? (double)Sp[3 * d + c] : (double)gld(M, g, 3 * d + c, kk - 1, oq);
         }
         const T iV = trcp(Vz);
         T R[5];
@@ -422,6 +435,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
         Qd[c] = Qn[c];
       }
       if (has_b) {
+        if (CS) load_q(Qin, g, oob, kk + 1, Bn);
         T bp[5];
         prim5(Bn, ph, bp);
 #pragma unroll
@@ -431,6 +445,10 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
         }
       }
       prim5(Qd, ph, Pd);
+      if (CS) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) Sp[c] = met[c];
+      }
 #pragma unroll
       for (int c = 0; c < 10; ++c) met[c] = metn[c];
       if (LAG == LAG_READ) { lag[0] = lagn[0]; lag[1] = lagn[1]; }

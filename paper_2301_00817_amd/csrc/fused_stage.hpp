@@ -85,12 +85,11 @@ template <typename T> struct PrefetchQ0 { static constexpr bool on = sizeof(T) =
 
 // The last stage of a step evaluates the next step's CFL sum at its output
 // point, which needs that point's metric terms, loaded two planes earlier
-// and no longer in L2 (a reload there cost the FP64 kernel 10 ms, a sixth
-// of the stage, on 1e9 points).  The FP64 kernel carries them from the
-// previous plane in registers instead, freed in that stage by loading Q^(0)
-// and the next plane's border where they are used rather than ahead; the
-// FP32 kernel has no registers for them (it spills) and reloads.
-template <typename T> struct CarryS { static constexpr bool on = sizeof(T) == 8; };
+// and no longer in L2 (reloading them cost the FP64 kernel 10 ms, a sixth
+// of the stage, on 1e9 points).  The stage carries them from the previous
+// plane in registers instead: FP64 frees the registers by loading Q^(0) and
+// the next plane's border where they are used rather than ahead; FP32 runs
+// that stage at three waves per SIMD (at four it spills).
 
 // Wave priority: the FP64 kernel (two waves per SIMD, bound by latency)
 // raises its waves' issue priority from the face phase to the end of the
@@ -102,10 +101,13 @@ template <typename T> struct CarryS { static constexpr bool on = sizeof(T) == 8;
 // gains nothing from it.
 template <typename T> struct WavePrio { static constexpr bool on = sizeof(T) == 8; };
 
-// Register budget: FP64 two waves per SIMD (up to 256 VGPRs), FP32 four (128).
+// Register budget: FP64 two waves per SIMD (up to 256 VGPRs), FP32 four
+// (128), three (168) in the last stage.
 template <typename T> struct FusedOcc;
 template <> struct FusedOcc<double> { static constexpr int waves = 2; };
 template <> struct FusedOcc<float> { static constexpr int waves = 4; };
+template <typename T, int EPI> struct FusedOccE { static constexpr int waves = FusedOcc<T>::waves; };
+template <> struct FusedOccE<float, EPI_RK_LAST> { static constexpr int waves = 3; };
 
 // AXIS: the eta- face is a centerline through mesh nodes (row j = 0 on the
 // axis); a separate instance so that the common case carries none of it.
@@ -115,7 +117,7 @@ template <> struct FusedOcc<float> { static constexpr int waves = 4; };
 // in every stage, so the points read are those written; points shared by
 // two blocks are written twice with the same value.
 template <typename T, int EPI, bool AXIS, int LAG, bool DYN>
-__global__ void __launch_bounds__(Tile<T>::X * Tile<T>::Y, FusedOcc<T>::waves)
+__global__ void __launch_bounds__(Tile<T>::X * Tile<T>::Y, (FusedOccE<T, EPI>::waves))
 k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_arg, int kc,
         TileMap tm, T* out, const double* Q0, double* Q64, double alpha,
         const double* __restrict__ dtp, Phys<double> ph64, unsigned long long* __restrict__ maxbits,
@@ -197,7 +199,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   T Qn[5];               // Q at kk+2, in flight
   T met[10], metn[10];   // metrics at (i, j, kk) and the prefetch for kk+1
   T lag[2], lagn[2];     // held (mu + mu_sgs, conductivity), same planes (LAG_READ)
-  constexpr bool CS = EPI == EPI_RK_LAST && CarryS<T>::on;
+  constexpr bool CS = EPI == EPI_RK_LAST;        // metric terms carried (above)
+  constexpr bool DEFER = CS && sizeof(T) == 8;    // loads deferred to free registers
   constexpr bool PQ0 = EPI != EPI_R && !CS && PrefetchQ0<T>::on;
   double q0p[5];         // Q^(0) at (i, j, kk-1), loaded at the top of iteration kk
   const double ad_pre = PQ0 ? alpha * (*dtp) : 0.0;
@@ -212,7 +215,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   T acc[5];              // RHS at kk-1 without its zeta face kk-1/2:
                          // in-plane faces minus the zeta face kk-3/2
   double lmax = 0.0;
-  T Sp[9];               // last stage (CS): metric terms of plane kk-1
+  T Sp[9];               // last stage: metric terms of plane kk-1
 
   {
     T q[5], pc[5];
@@ -311,7 +314,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     sE[7][ty][tx] = in.V;
     // border of the next plane, in flight during the face phase
     T Bn[5];
-    if (!CS && more && has_b) load_q(Qin, g, oob, kk + 1, Bn);
+    if (!DEFER && more && has_b) load_q(Qin, g, oob, kk + 1, Bn);
     __syncthreads();
 
     // (c) faces
@@ -372,7 +375,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
         // buffer accesses of different arrays by itself): Q^(0) of the output
         // point (loaded an iteration ahead where registers allow) and, at the
         // last stage, its metric terms for the next step's dt (carried in
-        // registers in FP64, reloaded in FP32)
+        // registers from the previous plane)
         double q0[5], S[3][3];
         if (EPI != EPI_R) {
 #pragma unroll
@@ -382,8 +385,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
 #pragma unroll
           for (int d = 0; d < 3; ++d)
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-              S[d][c] = CS ? (double)Sp[3 * d + c] : (double)gld(M, g, 3 * d + c, kk - 1, oq);
+            for (int c = 0; c < 3; ++c) S[d][c] = (double)Sp[3 * d + c];
         }
         const T iV = trcp(Vz);
         T R[5];
@@ -435,7 +437,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
         Qd[c] = Qn[c];
       }
       if (has_b) {
-        if (CS) load_q(Qin, g, oob, kk + 1, Bn);
+        if (DEFER) load_q(Qin, g, oob, kk + 1, Bn);
         T bp[5];
         prim5(Bn, ph, bp);
 #pragma unroll

@@ -80,7 +80,8 @@ struct TileMap {
 };
 
 // The FP64 kernel has registers left at two waves per SIMD: it loads Q^(0)
-// of the output point an iteration ahead (FP32 at 128 VGPRs does not).
+// of the output point an iteration ahead (FP32 at 128 VGPRs does not, nor
+// the FP64 last stage, whose registers carry metric terms instead).
 template <typename T> struct PrefetchQ0 { static constexpr bool on = sizeof(T) == 8; };
 
 // The last stage of a step evaluates the next step's CFL sum at its output
@@ -478,7 +479,8 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
 template <typename T>
 int fused_chunk(const Grid& g, int num_cu) {
   constexpr int FT_X = Tile<T>::X - 2, FT_Y = Tile<T>::Y - 2;
-  num_cu *= Tile<T>::PER_CU;          // resident blocks
+  num_cu *= Tile<T>::PER_CU;          // resident blocks (the FP32 last stage, at
+                                      // three per CU, takes the same length)
   const long long tiles = (long long)((g.nx + FT_X - 1) / FT_X) * ((g.nr + FT_Y - 1) / FT_Y);
   // pick the chunk length that minimises (rounds of resident blocks) x (planes per block),
   // over every length from 4 planes to the cap (lengths that divide the

@@ -203,6 +203,10 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
   constexpr bool CS = EPI == EPI_RK_LAST;        // metric terms carried (above)
   constexpr bool DEFER = CS && sizeof(T) == 8;    // loads deferred to free registers
   constexpr bool PQ0 = EPI != EPI_R && !CS && PrefetchQ0<T>::on;
+  // the own column two planes ahead is loaded at the top of the iteration
+  // in FP64 stages 1-4, after the point phase elsewhere (measured: the FP64
+  // last stage 2 % and FP32 stages 1 % faster, FP64 stages 1-4 4 % slower)
+  constexpr bool LATE_QN = sizeof(T) == 4 || CS;
   double q0p[5];         // Q^(0) at (i, j, kk-1), loaded at the top of iteration kk
   const double ad_pre = PQ0 ? alpha * (*dtp) : 0.0;
   auto load_lag = [&](int kk, T v[2]) {
@@ -253,9 +257,10 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
 
   for (int kk = k0 - 1; kk <= k1; ++kk) {
     const bool more = kk < k1;
-    // own-column and metric loads of the next plane, in flight during (b)
+    // metric loads of the next plane (and, early, the own column two planes
+    // ahead), in flight during (b)
     if (more) {
-      if (kk + 2 <= k1 + 1) load_q(Qin, g, oq, kk + 2, Qn);
+      if (!LATE_QN && kk + 2 <= k1 + 1) load_q(Qin, g, oq, kk + 2, Qn);
       load_metrics(M, g, oq, kk + 1, metn);
       if (LAG == LAG_READ) load_lag(kk + 1, lagn);
     }
@@ -316,6 +321,7 @@ k_fused(const T* __restrict__ Qin, const T* __restrict__ M, Grid g, Phys<T> ph_a
     // border of the next plane, in flight during the face phase
     T Bn[5];
     if (!DEFER && more && has_b) load_q(Qin, g, oob, kk + 1, Bn);
+    if (LATE_QN && more && kk + 2 <= k1 + 1) load_q(Qin, g, oq, kk + 2, Qn);
     __syncthreads();
 
     // (c) faces

@@ -221,6 +221,43 @@ def test_residual_chunk_boundaries(kchunk, monkeypatch):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rk5_steps_chunk_boundaries(precision, monkeypatch):
+    """Two RK5 steps under chunk lengths of 1, 3 and 7 planes.  The last
+    stage of a step takes each output plane's metric terms for the next
+    step's CFL sum from the previous plane of its chunk, so where chunks
+    start must not change the time steps beyond rounding (taking a
+    neighbouring plane's terms would change them by percents): they equal
+    those of the automatic chunking to 1e-13 (FP64; FP32 form 1e-6), the
+    states to 1e-14 (1e-6) of their maximum, and the time steps are the
+    oracle's (FP64 1e-12; the FP32 form's, from FP32 metrics, 1e-5).  A
+    chunk's first planes are formed by its prologue, compiled apart from
+    the march, so they may round differently by an ulp."""
+    announce("rk5-chunk", precision)
+    pb = CASES["jet37x22x20"]()
+    geo, inflow = _oracle(pb)
+    _, dts = les.run(pb["Q"].numpy(), geo, pb["params"], inflow, steps=2)
+    out = []
+    for kchunk in (None, 1, 3, 7):
+        if kchunk is None:
+            monkeypatch.delenv("LESJET_KCHUNK", raising=False)
+        else:
+            monkeypatch.setenv("LESJET_KCHUNK", str(kchunk))
+        s = make_solver(pb, precision=precision)
+        Qn = s.pad(pb["Q"].cuda(), dtype=torch.float64)
+        dt = to_np(s.rk5_step(Qn, 2))
+        out.append((kchunk, dt, to_np(s.interior(Qn))))
+        s.close()
+    dt_bar, q_bar = (1e-13, 1e-14) if precision == "fp64" else (1e-6, 1e-6)
+    for kchunk, dt, Q in out[1:]:
+        ddt = np.abs(dt / out[0][1] - 1).max()
+        dq = np.abs(Q - out[0][2]).max() / np.abs(out[0][2]).max()
+        print(f"{precision} kchunk {kchunk}: dt rel {ddt:.2e}, state rel {dq:.2e}")
+        assert ddt <= dt_bar
+        assert dq <= q_bar
+    assert np.abs(out[0][1] / np.asarray(dts) - 1).max() <= (1e-12 if precision == "fp64" else 1e-5)
+
+
 @pytest.mark.parametrize("shape", [(288, 160, 128), (401, 97, 64)])
 def test_fused_matches_two_pass_reference(shape):
     """Consistency of the fused kernel with the two-pass reference kernels on
